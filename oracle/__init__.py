@@ -1,0 +1,143 @@
+"""Oracle for the uniform multi-dimensional Jacobi transform.
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the CPU
+baseline leg of the benchmark may import this package.  The product library
+(C ABI + HIP kernels + its Python binding) never imports, links or calls it,
+and this package imports nothing from the product.
+
+What it computes (Section 3.1, eqs. (35)-(39); Section 3.2 eqs. (53)-(55);
+Section 3.3 eqs. (56)-(60)):
+
+* 1D:  A[j, k] = sqrt(omega_j) * phat_k(x_j), nodes ascending in t = arccos x,
+  built by the C routine in ``jacobi_oracle.c`` (long-double internals).
+  forward  g = A alpha,  inverse  alpha = A^T g  (A is orthogonal, Sec. 3.1).
+* dD:  the Kronecker product of the per-axis matrices: axis i of a row-major
+  tensor uses (n_i, a_i, b_i); forward applies A_i along every axis, inverse
+  applies A_i^T along every axis (eqs. (54), (55), (59), (60)).
+
+The apply step is a plain matrix product along each axis (numpy, fp64), with
+no blocking, reordering or fusion beyond that.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "jacobi_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libjacobi_oracle.so")
+_lib = None
+_cache: dict = {}
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle's C part (gcc, OpenMP).  Returns the library path."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        lib.orc_build.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp, dp]
+        lib.orc_build.restype = ctypes.c_int
+        lib.orc_recurrence.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp, dp]
+        lib.orc_recurrence.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(arr: np.ndarray):
+    return arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def matrix(n: int, a: float, b: float):
+    """Return (A, x, omega) for one axis; A is n x n row-major fp64, x descending."""
+    key = (int(n), float(a), float(b))
+    if key not in _cache:
+        lib = _load()
+        A = np.empty((n, n), dtype=np.float64)
+        x = np.empty(n, dtype=np.float64)
+        w = np.empty(n, dtype=np.float64)
+        rc = lib.orc_build(int(n), float(a), float(b), _ptr(A), _ptr(x), _ptr(w))
+        if rc != 0:
+            raise ValueError("oracle: invalid parameters n=%r a=%r b=%r" % (n, a, b))
+        _cache[key] = (A, x, w)
+    return _cache[key]
+
+
+def recurrence(n: int, a: float, b: float):
+    """Recurrence coefficients (alpha_0..alpha_n, beta_0..beta_n, mu0) of the oracle."""
+    lib = _load()
+    al = np.empty(n + 1)
+    be = np.empty(n + 1)
+    mu = np.empty(1)
+    rc = lib.orc_recurrence(int(n), float(a), float(b), _ptr(al), _ptr(be), _ptr(mu))
+    if rc != 0:
+        raise ValueError("oracle: invalid parameters")
+    return al, be, float(mu[0])
+
+
+def clear_cache() -> None:
+    _cache.clear()
+
+
+def _apply(x: np.ndarray, params, transpose: bool) -> np.ndarray:
+    x = np.asarray(x, dtype=np.float64)
+    if x.ndim != len(params):
+        raise ValueError("need one (a, b) pair per axis")
+    for axis, (a, b) in enumerate(params):
+        A = matrix(x.shape[axis], a, b)[0]
+        M = A.T if transpose else A
+        x = np.moveaxis(np.tensordot(M, x, axes=([1], [axis])), 0, axis)
+    return np.ascontiguousarray(x)
+
+
+def forward(alpha: np.ndarray, params) -> np.ndarray:
+    """g = (A_0 (x) A_1 (x) ...) alpha for a row-major tensor alpha."""
+    return _apply(alpha, params, transpose=False)
+
+
+def inverse(g: np.ndarray, params) -> np.ndarray:
+    """alpha = (A_0 (x) A_1 (x) ...)^T g."""
+    return _apply(g, params, transpose=True)
+
+
+def forward_entries(alpha: np.ndarray, params, index: np.ndarray) -> np.ndarray:
+    """Entries g[index[s]] of the forward transform, each computed on its own.
+
+    index: (S, d) integer array of output multi-indices.
+    """
+    return _entries(alpha, params, index, transpose=False)
+
+
+def inverse_entries(g: np.ndarray, params, index: np.ndarray) -> np.ndarray:
+    return _entries(g, params, index, transpose=True)
+
+
+def _entries(x, params, index, transpose):
+    x = np.asarray(x, dtype=np.float64)
+    d = x.ndim
+    mats = []
+    for axis, (a, b) in enumerate(params):
+        A = matrix(x.shape[axis], a, b)[0]
+        mats.append(A.T if transpose else A)
+    out = np.empty(len(index))
+    for s, idx in enumerate(np.asarray(index)):
+        t = x
+        # contract the last axis first with the needed row of its matrix
+        for axis in range(d - 1, -1, -1):
+            t = t @ mats[axis][idx[axis]]
+        out[s] = t
+    return out

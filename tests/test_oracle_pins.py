@@ -1,0 +1,215 @@
+"""Pins for the oracle: checks against facts fixed by the paper and by mathematics,
+never against the oracle's own formulas retyped.
+
+* a = b = -1/2: Chebyshev-T special case; A is the orthonormal DCT-III
+  (independent library routine: scipy.fft.dct).
+* a = b = +1/2: Chebyshev-U special case; A is the orthonormal DST-I.
+* brute force at tiny n with mpmath (40 digits): nodes bracketed by sign
+  changes of the explicit finite-sum P_n^(a,b), weights from the classical
+  derivative formula, norms from the Gamma-function closed form.
+* quadrature exactness (eq. (2): exact for degree <= 2n-1) against adaptive
+  algebraic-weight integration (scipy QAWS), which pins the measure, including
+  which endpoint carries a and which carries b.
+* orthogonality of W J (Section 3.1) at the benchmark sizes and the
+  forward-inverse identity.
+* the Kronecker axis convention (eqs. (54), (59)) against numpy.kron.
+* planted mistakes (swapped a/b, reversed node order) must fail the pins.
+"""
+import math
+
+import mpmath as mp
+import numpy as np
+import pytest
+import scipy.fft
+from scipy import integrate
+
+
+# ---------------------------------------------------------------- closed forms
+@pytest.mark.parametrize("n", [1, 2, 8, 64, 1000])
+def test_chebyshev_t_is_dct3(orc, n):
+    A, x, w = orc.matrix(n, -0.5, -0.5)
+    j = np.arange(1, n + 1)
+    np.testing.assert_allclose(x, np.cos((2 * j - 1) * np.pi / (2 * n)), rtol=0, atol=1e-15)
+    # the endpoint weights amplify the ~1e-19 node error of x-space long double
+    # arithmetic by ~1e5 (their Christoffel function is steep there)
+    np.testing.assert_allclose(w, np.full(n, np.pi / n), rtol=3e-14, atol=0)
+    al = np.random.default_rng(1).standard_normal(n)
+    ref = scipy.fft.dct(al, type=3, norm="ortho")
+    assert np.abs(A @ al - ref).max() <= 5e-14 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("n", [1, 3, 8, 64, 1000])
+def test_chebyshev_u_is_dst1(orc, n):
+    A, x, w = orc.matrix(n, 0.5, 0.5)
+    j = np.arange(1, n + 1)
+    np.testing.assert_allclose(x, np.cos(j * np.pi / (n + 1)), rtol=0, atol=1e-15)
+    al = np.random.default_rng(2).standard_normal(n)
+    ref = scipy.fft.dst(al, type=1, norm="ortho")
+    assert np.abs(A @ al - ref).max() <= 5e-14 * max(1.0, np.abs(ref).max())
+
+
+# ------------------------------------------------------------ mpmath brute force
+def _mp_matrix(n, a, b, dps=40):
+    """Dense A for tiny n from explicit Jacobi polynomials in multiprecision."""
+    with mp.workdps(dps):
+        a_, b_ = mp.mpf(a), mp.mpf(b)
+
+        def jac(k, al, be, x):
+            # explicit finite sum: P_k^(al,be)(x) =
+            #   sum_s C(k+al, k-s) C(k+be, s) ((x-1)/2)^s ((x+1)/2)^(k-s)
+            xm, xp = (x - 1) / 2, (x + 1) / 2
+            return mp.fsum(mp.binomial(k + al, k - s) * mp.binomial(k + be, s)
+                           * xm ** s * xp ** (k - s) for s in range(k + 1))
+
+        def pn(t):
+            return jac(n, a_, b_, mp.cos(t))
+
+        m = 40 * n
+        grid = [mp.pi * i / m for i in range(1, m)]
+        vals = [pn(t) for t in grid]
+        ts = []
+        for i in range(len(grid) - 1):
+            if vals[i] == 0:
+                ts.append(grid[i])
+            elif vals[i] * vals[i + 1] < 0:
+                ts.append(mp.findroot(pn, (grid[i], grid[i + 1]), solver="anderson"))
+        assert len(ts) == n, (len(ts), n)
+        xs = [mp.cos(t) for t in ts]  # ascending t
+        # classical Gauss-Jacobi weight:  Gamma ratio * 2^(a+b+1) / ((1-x^2) P_n'(x)^2),
+        # with P_n' = (n+a+b+1)/2 * P_{n-1}^(a+1,b+1)
+        cst = (mp.gamma(n + a_ + 1) * mp.gamma(n + b_ + 1)
+               / (mp.gamma(n + a_ + b_ + 1) * mp.factorial(n)) * mp.power(2, a_ + b_ + 1))
+
+        def dpn(x):
+            if n == 0:
+                return mp.mpf(0)
+            return (n + a_ + b_ + 1) / 2 * jac(n - 1, a_ + 1, b_ + 1, x)
+
+        ws = [cst / ((1 - x * x) * dpn(x) ** 2) for x in xs]
+
+        def hk(k):
+            if k == 0:
+                return mp.power(2, a_ + b_ + 1) * mp.gamma(a_ + 1) * mp.gamma(b_ + 1) / mp.gamma(a_ + b_ + 2)
+            return (mp.power(2, a_ + b_ + 1) / (2 * k + a_ + b_ + 1)
+                    * mp.gamma(k + a_ + 1) * mp.gamma(k + b_ + 1)
+                    / (mp.gamma(k + a_ + b_ + 1) * mp.factorial(k)))
+
+        norms = [mp.sqrt(hk(k)) for k in range(n)]
+        A = np.empty((n, n))
+        for j, x in enumerate(xs):
+            sw = mp.sqrt(ws[j])
+            for k in range(n):
+                A[j, k] = float(sw * jac(k, a_, b_, x) / norms[k])
+        return A, np.array([float(x) for x in xs]), np.array([float(w) for w in ws])
+
+
+BRUTE_PAIRS = [(0.0, 0.0), (0.25, -0.35), (-0.4, 0.1), (0.3, 0.3), (0.3, -0.3),
+               (-0.5, -0.5), (0.9, -0.9), (-0.75, 0.6)]
+
+
+@pytest.mark.parametrize("a,b", BRUTE_PAIRS)
+@pytest.mark.parametrize("n", [1, 5, 16])
+def test_brute_force_mpmath(orc, n, a, b):
+    A_ref, x_ref, w_ref = _mp_matrix(n, a, b)
+    A, x, w = orc.matrix(n, a, b)
+    np.testing.assert_allclose(x, x_ref, rtol=0, atol=2e-16 * 4)
+    np.testing.assert_allclose(w, w_ref, rtol=1e-14, atol=0)
+    assert np.abs(A - A_ref).max() <= 1e-14
+    # and the transform of a random vector
+    al = np.random.default_rng(n).standard_normal(n)
+    assert np.abs(A @ al - A_ref @ al).max() <= 1e-14 * max(1.0, np.abs(A_ref @ al).max())
+
+
+@pytest.mark.slow
+def test_brute_force_mpmath_legendre_n48(orc):
+    A_ref, _, _ = _mp_matrix(48, 0.0, 0.0, dps=30)
+    A, _, _ = orc.matrix(48, 0.0, 0.0)
+    assert np.abs(A - A_ref).max() <= 1e-14
+
+
+# ------------------------------------------------------------ quadrature exactness
+@pytest.mark.parametrize("a,b", [(0.25, -0.35), (-0.4, 0.1), (0.3, 0.3), (0.7, -0.2), (-0.9, 0.45)])
+def test_quadrature_exact_to_degree_2n_minus_1(orc, a, b):
+    n = 12
+    _, x, w = orc.matrix(n, a, b)
+    for k in range(2 * n):
+        f = lambda s, k=k: math.cos(k * math.acos(max(-1.0, min(1.0, s))))
+        # QAWS: integral of (s+1)^b (1-s)^a f(s) over [-1, 1]
+        ref, err = integrate.quad(f, -1.0, 1.0, weight="alg", wvar=(b, a), limit=200,
+                                  epsabs=1e-14, epsrel=1e-13)
+        got = float(np.sum(w * np.cos(k * np.arccos(x))))
+        assert abs(got - ref) <= 2e-13 * max(1.0, abs(ref)), (k, got, ref)
+
+
+# ------------------------------------------------------------ orthogonality at size
+@pytest.mark.parametrize("n,a,b", [(1024, 0.25, -0.35), (1024, -0.4, 0.1), (256, 0.3, 0.3)])
+def test_orthogonal_at_benchmark_sizes(orc, n, a, b):
+    A, _, _ = orc.matrix(n, a, b)
+    assert np.linalg.norm(A.T @ A - np.eye(n), 2) <= 1e-13
+    al = np.random.default_rng(7).standard_normal(n)
+    rt = A.T @ (A @ al)
+    assert np.linalg.norm(rt - al) / np.linalg.norm(al) <= 1e-14
+
+
+def test_forward_inverse_identity_2d(orc):
+    params = ((0.25, -0.35), (-0.4, 0.1))
+    al = np.random.default_rng(3).standard_normal((64, 48))
+    g = orc.forward(al, params)
+    back = orc.inverse(g, params)
+    assert np.linalg.norm(back - al) / np.linalg.norm(al) <= 1e-14
+    assert abs(np.linalg.norm(g) - np.linalg.norm(al)) <= 1e-13 * np.linalg.norm(al)
+
+
+# ------------------------------------------------------------ Kronecker convention
+def test_kronecker_axis_convention_2d(orc):
+    params = ((0.25, -0.35), (-0.4, 0.1))
+    n0, n1 = 5, 7
+    al = np.random.default_rng(4).standard_normal((n0, n1))
+    A0 = orc.matrix(n0, *params[0])[0]
+    A1 = orc.matrix(n1, *params[1])[0]
+    ref = (np.kron(A0, A1) @ al.reshape(-1)).reshape(n0, n1)
+    np.testing.assert_allclose(orc.forward(al, params), ref, rtol=0, atol=1e-14)
+    ref_inv = (np.kron(A0, A1).T @ al.reshape(-1)).reshape(n0, n1)
+    np.testing.assert_allclose(orc.inverse(al, params), ref_inv, rtol=0, atol=1e-14)
+
+
+def test_kronecker_axis_convention_3d(orc):
+    params = ((0.1, 0.2), (-0.3, 0.4), (0.45, -0.15))
+    shape = (3, 4, 5)
+    al = np.random.default_rng(5).standard_normal(shape)
+    K = np.kron(np.kron(orc.matrix(3, *params[0])[0], orc.matrix(4, *params[1])[0]),
+                orc.matrix(5, *params[2])[0])
+    np.testing.assert_allclose(orc.forward(al, params), (K @ al.reshape(-1)).reshape(shape),
+                               rtol=0, atol=1e-14)
+
+
+def test_sampled_entries_match_full(orc):
+    params = ((0.3, 0.3),) * 3
+    al = np.random.default_rng(6).standard_normal((9, 10, 11))
+    g = orc.forward(al, params)
+    idx = np.array([[0, 0, 0], [8, 9, 10], [4, 2, 7]])
+    np.testing.assert_allclose(orc.forward_entries(al, params, idx), g[tuple(idx.T)], atol=1e-14)
+    a = orc.inverse(g, params)
+    np.testing.assert_allclose(orc.inverse_entries(g, params, idx), a[tuple(idx.T)], atol=1e-14)
+
+
+# ------------------------------------------------------------ planted mistakes
+def test_pins_catch_swapped_parameters(orc):
+    """An oracle that swapped a and b (the endpoint convention) fails brute force."""
+    A_ref, _, _ = _mp_matrix(8, 0.25, -0.35)
+    A_bad, _, _ = orc.matrix(8, -0.35, 0.25)
+    assert np.abs(A_bad - A_ref).max() > 1e-3
+
+
+def test_pins_catch_reversed_node_order(orc):
+    A, _, _ = orc.matrix(16, -0.5, -0.5)
+    al = np.random.default_rng(8).standard_normal(16)
+    ref = scipy.fft.dct(al, type=3, norm="ortho")
+    assert np.abs(A[::-1] @ al - ref).max() > 1e-3
+
+
+def test_rejects_invalid_parameters(orc):
+    with pytest.raises(ValueError):
+        orc.matrix(8, -1.0, 0.0)
+    with pytest.raises(ValueError):
+        orc.matrix(0, 0.0, 0.0)
