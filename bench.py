@@ -1,0 +1,198 @@
+"""Benchmark: 2D uniform Jacobi transform, 1024 x 1024, forward + inverse.
+
+One step = one forward and one inverse transform of a 1024 x 1024 tensor
+(axis 0: (a, b) = (0.25, -0.35), axis 1: (-0.4, 0.1), low-rank tol 1e-12),
+with the input already resident in HBM.  Both precisions are timed: the
+fp32-bulk path (fp32 factors/FFTs, fp64 rank-sum accumulation) gives
+`value`; the plain fp64 path is reported beside it.  Each step is four
+axis-pass launches (forward axis 1, forward axis 0, inverse axis 1,
+inverse axis 0), each bracketed by HIP events on the launch stream, which
+gives per-launch durations for the roofline and per-step latencies for
+p50/p99.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads  # noqa: E402
+
+PEAK_FP64 = 78.6e12   # MI355X fp64 vector, FLOP/s
+PEAK_FP32 = 157.3e12  # MI355X fp32 vector, FLOP/s (packed); unpacked issue reaches half of it
+
+
+def axis_flops(n: int, L: int, nu0: int, rank: int, lines: int) -> float:
+    """Algorithmic flops of one axis pass: per line r complex L-point FFTs
+    (5 L log2 L each), the diagonal scalings and gather-accumulate (8 n per
+    term) and the direct block (2 nu0 n)."""
+    per_line = rank * (5.0 * L * math.log2(L) + 8.0 * n) + 2.0 * nu0 * n
+    return per_line * lines
+
+
+def percentile(xs, q):
+    return float(np.percentile(np.asarray(xs), q))
+
+
+def time_path(jt, torch, plan, alpha, prec, steps, warmup):
+    dev = alpha.device
+    g = torch.empty_like(alpha)
+    back = torch.empty_like(alpha)
+    stream = torch.cuda.current_stream(dev)
+    launches = [(1, jt.FORWARD, alpha, g), (0, jt.FORWARD, g, g),
+                (1, jt.INVERSE, g, back), (0, jt.INVERSE, back, back)]
+
+    def step(record):
+        evs = []
+        if record:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            evs.append(e0)
+        for axis, d, src, dst in launches:
+            plan.apply_axis(axis, d, src, dst, prec=prec, stream=stream)
+            if record:
+                e = torch.cuda.Event(enable_timing=True)
+                e.record(stream)
+                evs.append(e)
+        return evs
+
+    for _ in range(warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    all_evs = [step(True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms, launch_ms = [], [[] for _ in launches]
+    for evs in all_evs:
+        step_ms.append(evs[0].elapsed_time(evs[-1]))
+        for i in range(len(launches)):
+            launch_ms[i].append(evs[i].elapsed_time(evs[i + 1]))
+    return wall, step_ms, launch_ms, g, back
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(one GPU's share of the work is the whole workload); run with --gpus 1", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_1901_07275_amd as jt
+
+    cfg = workloads.C2
+    dev = torch.device("cuda:0")
+    t_plan = time.perf_counter()
+    plan = jt.Plan(cfg["n"], cfg["ab"], cfg["tol"]).bind(dev)
+    t_plan = time.perf_counter() - t_plan
+    infos = [plan.info(i) for i in range(plan.d)]
+    al_np = workloads.config_input(cfg)
+    alpha = torch.from_numpy(al_np).to(dev)
+    n0, n1 = cfg["n"]
+    coeffs = n0 * n1
+
+    results = {}
+    for name, prec in (("fp64", jt.PREC_FP64), ("fp32", jt.PREC_FP32_BULK)):
+        wall, step_ms, launch_ms, g, back = time_path(jt, torch, plan, alpha, prec, args.steps, args.warmup)
+        ms = float(np.mean(step_ms))
+        flops = [axis_flops(infos[1]["n"], infos[1]["L"], infos[1]["nu0"], infos[1]["rank"], n0),
+                 axis_flops(infos[0]["n"], infos[0]["L"], infos[0]["nu0"], infos[0]["rank"], n1)]
+        launch_avg = [float(np.mean(x)) for x in launch_ms]
+        launch_flops = [flops[0], flops[1], flops[0], flops[1]]
+        results[name] = dict(ms_per_step=ms, p50_ms=percentile(step_ms, 50), p99_ms=percentile(step_ms, 99),
+                             wall_s=wall, value=2.0 * coeffs / (ms * 1e-3),
+                             launch_ms=launch_avg, launch_flops=launch_flops,
+                             g=g.cpu().numpy(), back=back.cpu().numpy())
+
+    # accuracy against the oracle (outside the timed region)
+    import oracle
+
+    g_ref = oracle.forward(al_np, cfg["ab"])
+    for name in results:
+        r = results[name]
+        r["rel_l2_forward"] = float(np.linalg.norm(r["g"] - g_ref) / np.linalg.norm(g_ref))
+        r["rel_l2_roundtrip"] = float(np.linalg.norm(r["back"] - al_np) / np.linalg.norm(al_np))
+        del r["g"], r["back"]
+
+    # roofline of the dominant kernel (the axis pass) for the headline path
+    head = results["fp32"]
+    avg_launch_ms = float(np.mean(head["launch_ms"]))
+    avg_launch_flops = float(np.mean(head["launch_flops"]))
+    achieved = avg_launch_flops / (avg_launch_ms * 1e-3) / 1e12
+    roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / (PEAK_FP32 / 1e12), "traffic": None,
+            "kernel": "axis_pass<float,10>", "launch_ms": avg_launch_ms, "flops_per_launch": avg_launch_flops}
+    r64 = results["fp64"]
+    ach64 = float(np.mean(r64["launch_flops"])) / (float(np.mean(r64["launch_ms"])) * 1e-3) / 1e12
+    r64["roofline"] = {"bound": "alu", "achieved": ach64, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
+                       "frac": ach64 / (PEAK_FP64 / 1e12), "kernel": "axis_pass<double,10>"}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        reps, t_used = 0, 0.0
+        t0 = time.perf_counter()
+        while t_used < args.cpu_seconds or reps == 0:
+            gg = oracle.forward(al_np, cfg["ab"])
+            oracle.inverse(gg, cfg["ab"])
+            reps += 1
+            t_used = time.perf_counter() - t0
+        try:
+            from threadpoolctl import threadpool_info
+
+            cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [os.cpu_count() or 1])
+        except Exception:
+            cores = os.cpu_count() or 1
+        cpu = {"value": 2.0 * coeffs * reps / t_used, "unit": "coeffs/s", "cores": int(cores), "kind": "oracle",
+               "sample": "%d forward+inverse passes of the full 1024x1024 workload (dense oracle matrices "
+                         "applied along each axis in fp64), %.1f s" % (reps, t_used)}
+
+    line = {
+        "metric": "coeffs/s, 2D n=1024 Jacobi FP32 vs FP64 at stated rel-l2; p50/p99 latency",
+        "value": head["value"],
+        "unit": "coeffs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "2d_n1024_forward_plus_inverse", "n": list(cfg["n"]),
+                   "ab": [list(p) for p in cfg["ab"]], "tol": cfg["tol"],
+                   "ranks": [i["rank"] for i in infos], "plan_seconds": t_plan,
+                   "step": "one forward + one inverse transform (4 axis-pass launches)"},
+        "p50_ms": head["p50_ms"],
+        "p99_ms": head["p99_ms"],
+        "rel_l2_forward": head["rel_l2_forward"],
+        "rel_l2_roundtrip": head["rel_l2_roundtrip"],
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "fp64": results["fp64"],
+        "fp32": {k: v for k, v in results["fp32"].items()},
+    }
+    print(json.dumps(line))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,186 @@
+/*
+ * jt.h -- C ABI of the MI355X fast multi-dimensional Jacobi transform.
+ *
+ * The library applies the uniform forward and inverse Jacobi polynomial
+ * transform on tensor-product Gauss-Jacobi grids in 1, 2 or 3 dimensions, by
+ * the method of Bremer, Pang and Yang, "Fast algorithms for the
+ * multi-dimensional Jacobi polynomial transform" (arXiv:1901.07275):
+ *
+ *   * 1D (Section 3.1, eqs. (35)-(39)): the orthogonal n x n matrix W J with
+ *     (W J)_{jk} = sqrt(w_j) Ptilde_k(t_j) = sqrt(omega_j) phat_k(x_j), where
+ *     x_j = cos t_j are the Gauss-Jacobi nodes for (1-x)^a (1+x)^b ordered by
+ *     ascending t, omega_j the Gauss-Jacobi weights and phat_k the
+ *     orthonormal Jacobi polynomials.  It is applied as the direct block of
+ *     degrees < 27 plus r diagonally scaled inverse FFTs (eq. (50)); the
+ *     inverse is the transpose (eq. (51)).
+ *   * dD (Sections 3.2-3.3, eqs. (54), (55), (59), (60)): the Kronecker
+ *     product of the per-axis matrices, applied axis by axis.
+ *
+ * Conventions shared by every entry point
+ *   - Tensors are contiguous, row-major, shape (n[0], ..., n[d-1]).  Axis i
+ *     uses the parameters (n[i], a[i], b[i]).  Element [k0, k1, ...] of a
+ *     coefficient tensor multiplies phat_{k0} (x) phat_{k1} (x) ...; element
+ *     [j0, j1, ...] of a value tensor is the weighted value at the node tuple
+ *     (t_{j0}, t_{j1}, ...).
+ *   - forward: g = (W0 J0 (x) W1 J1 (x) ...) alpha.
+ *     inverse: alpha = (W0 J0 (x) W1 J1 (x) ...)^T g.  Both are orthogonal.
+ *   - Device buffers are owned by the caller.  The library never allocates
+ *     device memory; it allocates host memory only inside jt_plan*.
+ *   - Every call returns a jt_status; no exception crosses the ABI.  On error
+ *     jt_last_error() returns a message for the calling thread.  Kernel
+ *     launch failures are reported as JT_EDEVICE; faults during execution
+ *     surface at the caller's next synchronisation on the stream.
+ *   - A plan is immutable after jt_plan_bind; a bound plan may be used from
+ *     several streams at once (kernels only read the bound factors).
+ */
+#ifndef JT_H
+#define JT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct jt_plan_s *jt_plan_t;
+
+typedef enum {
+    JT_OK = 0,
+    JT_EINVAL = 1,         /* invalid argument */
+    JT_ENOMEM = 2,         /* host allocation failed, or a device buffer is too small */
+    JT_EDEVICE = 3,        /* HIP runtime or kernel-launch error */
+    JT_ENOTCONV = 4,       /* node search or randomized SVD did not converge */
+    JT_EUNSUPPORTED = 5,   /* size/precision combination not built */
+    JT_ESTATE = 6          /* plan not bound to device memory */
+} jt_status;
+
+typedef enum { JT_F64 = 0, JT_F32 = 1 } jt_dtype;
+
+typedef enum {
+    JT_PREC_FP64 = 0,      /* fp64 factors, twiddles, FFTs and accumulation */
+    JT_PREC_FP32_BULK = 1  /* fp32 factors, twiddles and FFTs; fp64 rank-sum accumulation.
+                              Phases and bins are always fixed on the host in fp64/long double. */
+} jt_prec;
+
+typedef enum { JT_FORWARD = 0, JT_INVERSE = 1 } jt_direction;
+
+/* Optional planning knobs; jt_plan() uses the defaults listed here. */
+typedef struct {
+    int nu0;          /* width of the direct (low-degree) block; default 27 (Section 3.1) */
+    int dense_below;  /* n below this uses the direct block for all degrees; default 64 */
+    int oversample;   /* q of Algorithm 2.1; default 2 */
+    int iterations;   /* repetitions of steps 2-3 of Algorithm 2.1; default 2 (Section 2.1) */
+    uint64_t seed;    /* 0: derived from (n, a, b, tol), so plans are reproducible */
+} jt_plan_options;
+
+/* Per-axis facts about a plan. */
+typedef struct {
+    int n;            /* points and degrees on this axis */
+    int L;            /* FFT length: smallest power of two >= max(n, 64) */
+    int nu0;          /* direct-block width */
+    int rank;         /* r: number of FFTs per line (eq. (50)) */
+    int max_per_bin;  /* most nodes sharing one DFT bin [t_j L / 2 pi] */
+    int rsvd_rounds;  /* rank-growth rounds Algorithm 2.1 needed */
+    double rel_err;   /* measured ||W B - sum_l u_l v_l^T||_F / ||W B||_F */
+    double fro;       /* ||W B||_F */
+} jt_axis_info;
+
+/*
+ * Build a plan on the host (fp64 / long double).  For each axis: Gauss-Jacobi
+ * nodes and weights (eq. (2), eq. (9)), DFT bins (eq. (45)), the direct block,
+ * and the rank-r factors of the weighted low-rank matrix W B (eq. (45)) by
+ * Algorithm 2.1 (randomized sampling, pivoted QR/LQ, middle matrix, SVD), with
+ * the rank grown until the relative Frobenius error is at most tol.
+ *   d    : 1, 2 or 3
+ *   n    : d sizes, 1 <= n[i] <= 16384
+ *   a, b : d Jacobi parameters each, in (-1, 1) (the paper's analysis covers
+ *          (-1/2, 1/2); its experiments also use (-1, 1))
+ *   tol  : low-rank relative tolerance, in [1e-14, 1e-2]
+ *   out  : receives the plan handle (owned by the caller; free with jt_plan_destroy)
+ * Errors: JT_EINVAL (bad argument), JT_ENOMEM, JT_ENOTCONV.
+ */
+jt_status jt_plan(int d, const int *n, const double *a, const double *b, double tol, jt_plan_t *out);
+
+/* As jt_plan, with explicit options (opt may be NULL for the defaults). */
+jt_status jt_plan_ex(int d, const int *n, const double *a, const double *b, double tol,
+                     const jt_plan_options *opt, jt_plan_t *out);
+
+/* Release a plan (host memory only; the caller still owns the bound device buffer).
+ * NULL is accepted. */
+jt_status jt_plan_destroy(jt_plan_t plan);
+
+/* Number of axes of the plan. */
+jt_status jt_plan_dims(jt_plan_t plan, int *d);
+
+/* Per-axis facts (axis in [0, d)). */
+jt_status jt_plan_info(jt_plan_t plan, int axis, jt_axis_info *info);
+
+/* Copy the axis' nodes t_j (ascending), x_j = cos t_j and Gauss-Jacobi weights
+ * omega_j into caller host arrays of length n.  Any pointer may be NULL. */
+jt_status jt_plan_nodes(jt_plan_t plan, int axis, double *t, double *x, double *omega);
+
+/* Copy the axis' factors to caller host arrays (any pointer may be NULL):
+ *   bins : n int32, m_j = [t_j L / 2 pi] in [0, L/2] (eq. (45), eq. (47))
+ *   wv   : nu0 * n fp64, wv[k*n + j] = sqrt(omega_j) phat_k(x_j) (direct block)
+ *   u    : rank * n complex fp64 (re, im interleaved), u[l*n + j] = (W U S^1/2)_{j,l}
+ *   v    : rank * (n - nu0) complex fp64, v[l*(n-nu0) + c] = (S^1/2 V)_{l,c},
+ *          column c standing for degree nu0 + c (eq. (49)). */
+jt_status jt_plan_factors(jt_plan_t plan, int axis, int32_t *bins, double *wv, double *u, double *v);
+
+/* Exact entries of W B (eq. (45), weights folded in) at (row j, degree k),
+ * nu0 <= k < n, computed on the host in long double; out holds count complex
+ * values (re, im interleaved).  For diagnostics. */
+jt_status jt_plan_entries(jt_plan_t plan, int axis, int count, const int *rows, const int *degrees,
+                          double *out);
+
+/* Bytes of device memory the bound factors need. */
+jt_status jt_plan_device_bytes(jt_plan_t plan, size_t *bytes);
+
+/* Copy the packed factors into the caller's device buffer dev_buf (at least
+ * jt_plan_device_bytes bytes, 256-byte aligned) with one asynchronous copy on
+ * `stream` (a hipStream_t; NULL = default stream).  The plan keeps the pointer;
+ * the buffer must stay allocated and unmodified while the plan is used.
+ * Errors: JT_EINVAL, JT_ENOMEM (buffer too small), JT_EDEVICE. */
+jt_status jt_plan_bind(jt_plan_t plan, void *dev_buf, size_t bytes, void *stream);
+
+/* Device workspace a transform needs beyond its input and output: always 0
+ * (every axis pass works in place on the output buffer). */
+jt_status jt_workspace_bytes(jt_plan_t plan, jt_prec prec, size_t *bytes);
+
+/*
+ * Forward transform g = (W0 J0 (x) ... ) alpha on device buffers.
+ *   alpha_dev : input, prod n[i] elements of dtype `in`
+ *   g_dev     : output, prod n[i] elements of dtype `out`; may equal alpha_dev
+ *               only when in == out
+ *   prec      : arithmetic of the FFT bulk (jt_prec)
+ *   stream    : hipStream_t to launch on (NULL = default stream)
+ * One kernel launch per axis (axes d-1, ..., 0), no host synchronisation.
+ * With d > 1 the intermediate results live in g_dev, in dtype `out`.
+ * Errors: JT_EINVAL, JT_ESTATE (not bound), JT_EUNSUPPORTED, JT_EDEVICE.
+ */
+jt_status jt_forward(jt_plan_t plan, const void *alpha_dev, jt_dtype in, void *g_dev, jt_dtype out,
+                     jt_prec prec, void *stream);
+
+/* Inverse transform alpha = (W0 J0 (x) ... )^T g (eqs. (51), (55), (60)); same
+ * argument rules as jt_forward. */
+jt_status jt_inverse(jt_plan_t plan, const void *g_dev, jt_dtype in, void *alpha_dev, jt_dtype out,
+                     jt_prec prec, void *stream);
+
+/* One axis pass only: applies W_i J_i (JT_FORWARD) or its transpose
+ * (JT_INVERSE) along axis `axis` of the full tensor.  in_dev and out_dev may be
+ * the same buffer (in place) when in == out.  Same errors as jt_forward. */
+jt_status jt_apply_axis(jt_plan_t plan, int axis, jt_direction dir, const void *in_dev, jt_dtype in,
+                        void *out_dev, jt_dtype out, jt_prec prec, void *stream);
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char *jt_last_error(void);
+
+/* ABI version of this header (major * 100 + minor). */
+int jt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JT_H */

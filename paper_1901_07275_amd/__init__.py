@@ -1,0 +1,238 @@
+"""Python binding of the MI355X fast multi-dimensional Jacobi transform.
+
+Thin ctypes marshalling over the C ABI in include/jt.h (libjt.so, built
+in-tree by ``paper_1901_07275_amd.build``).  Every step of the transform runs
+in the library's HIP kernels; torch is used only to hold device memory and
+to name the stream.  There is no CPU fallback: if libjt.so is missing the
+import fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libjt.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        "libjt.so not found at %s; build it with `python -m paper_1901_07275_amd.build`" % LIB_PATH)
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+JT_OK, JT_EINVAL, JT_ENOMEM, JT_EDEVICE, JT_ENOTCONV, JT_EUNSUPPORTED, JT_ESTATE = range(7)
+F64, F32 = 0, 1
+PREC_FP64, PREC_FP32_BULK = 0, 1
+FORWARD, INVERSE = 0, 1
+_STATUS = {0: "JT_OK", 1: "JT_EINVAL", 2: "JT_ENOMEM", 3: "JT_EDEVICE", 4: "JT_ENOTCONV",
+           5: "JT_EUNSUPPORTED", 6: "JT_ESTATE"}
+
+
+class PlanOptions(ctypes.Structure):
+    _fields_ = [("nu0", ctypes.c_int), ("dense_below", ctypes.c_int), ("oversample", ctypes.c_int),
+                ("iterations", ctypes.c_int), ("seed", ctypes.c_uint64)]
+
+
+class AxisInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("L", ctypes.c_int), ("nu0", ctypes.c_int), ("rank", ctypes.c_int),
+                ("max_per_bin", ctypes.c_int), ("rsvd_rounds", ctypes.c_int),
+                ("rel_err", ctypes.c_double), ("fro", ctypes.c_double)]
+
+
+_vp = ctypes.c_void_p
+_ip = ctypes.POINTER(ctypes.c_int)
+_dp = ctypes.POINTER(ctypes.c_double)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+
+# name -> (argtypes)
+SYMBOLS = {
+    "jt_plan": [ctypes.c_int, _ip, _dp, _dp, ctypes.c_double, ctypes.POINTER(_vp)],
+    "jt_plan_ex": [ctypes.c_int, _ip, _dp, _dp, ctypes.c_double, ctypes.POINTER(PlanOptions),
+                   ctypes.POINTER(_vp)],
+    "jt_plan_destroy": [_vp],
+    "jt_plan_dims": [_vp, _ip],
+    "jt_plan_info": [_vp, ctypes.c_int, ctypes.POINTER(AxisInfo)],
+    "jt_plan_nodes": [_vp, ctypes.c_int, _dp, _dp, _dp],
+    "jt_plan_factors": [_vp, ctypes.c_int, _i32p, _dp, _dp, _dp],
+    "jt_plan_entries": [_vp, ctypes.c_int, ctypes.c_int, _ip, _ip, _dp],
+    "jt_plan_device_bytes": [_vp, ctypes.POINTER(ctypes.c_size_t)],
+    "jt_plan_bind": [_vp, _vp, ctypes.c_size_t, _vp],
+    "jt_workspace_bytes": [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)],
+    "jt_forward": [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp],
+    "jt_inverse": [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp],
+    "jt_apply_axis": [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int,
+                      _vp],
+}
+for _name, _args in SYMBOLS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = ctypes.c_int
+_lib.jt_last_error.restype = ctypes.c_char_p
+_lib.jt_last_error.argtypes = []
+_lib.jt_version.restype = ctypes.c_int
+_lib.jt_version.argtypes = []
+
+
+class JTError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (_STATUS.get(status, str(status)), msg))
+        self.status = status
+
+
+def _check(st: int) -> None:
+    if st != JT_OK:
+        raise JTError(st, _lib.jt_last_error().decode(errors="replace"))
+
+
+def version() -> int:
+    return _lib.jt_version()
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(_dp)
+
+
+class Plan:
+    """A d-dimensional uniform Jacobi transform plan (d = 1, 2, 3).
+
+    n: sizes per axis; ab: (a, b) per axis; tol: low-rank tolerance.
+    """
+
+    def __init__(self, n: Sequence[int], ab: Sequence[Sequence[float]], tol: float,
+                 nu0: int = 0, dense_below: int = -1, oversample: int = 0, iterations: int = 0,
+                 seed: int = 0):
+        self.n = tuple(int(v) for v in n)
+        self.ab = tuple((float(a), float(b)) for a, b in ab)
+        if len(self.ab) != len(self.n):
+            raise ValueError("need one (a, b) pair per axis")
+        self.tol = float(tol)
+        d = len(self.n)
+        nn = (ctypes.c_int * d)(*self.n)
+        aa = (ctypes.c_double * d)(*[p[0] for p in self.ab])
+        bb = (ctypes.c_double * d)(*[p[1] for p in self.ab])
+        opt = PlanOptions(nu0, dense_below, oversample, iterations, seed)
+        h = _vp()
+        _check(_lib.jt_plan_ex(d, nn, aa, bb, self.tol, ctypes.byref(opt), ctypes.byref(h)))
+        self._h = h
+        self._dev = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.jt_plan_destroy(h)
+            self._h = None
+
+    @property
+    def d(self) -> int:
+        return len(self.n)
+
+    def info(self, axis: int) -> dict:
+        inf = AxisInfo()
+        _check(_lib.jt_plan_info(self._h, axis, ctypes.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in AxisInfo._fields_}
+
+    def nodes(self, axis: int):
+        n = self.n[axis]
+        t, x, w = np.empty(n), np.empty(n), np.empty(n)
+        _check(_lib.jt_plan_nodes(self._h, axis, _dptr(t), _dptr(x), _dptr(w)))
+        return t, x, w
+
+    def factors(self, axis: int):
+        """Host copies (bins, WV (nu0 x n), U (r x n complex), V (r x (n-nu0) complex))."""
+        inf = self.info(axis)
+        n, nu0, r = inf["n"], inf["nu0"], inf["rank"]
+        bins = np.empty(n, dtype=np.int32)
+        wv = np.empty(nu0 * n)
+        u = np.empty(2 * r * n)
+        v = np.empty(2 * r * (n - nu0))
+        _check(_lib.jt_plan_factors(self._h, axis, bins.ctypes.data_as(_i32p), _dptr(wv), _dptr(u),
+                                    _dptr(v)))
+        U = u.view(np.complex128).reshape(r, n)
+        V = v.view(np.complex128).reshape(r, n - nu0)
+        return bins, wv.reshape(nu0, n), U, V
+
+    def entries(self, axis: int, rows, degrees) -> np.ndarray:
+        rows = np.ascontiguousarray(rows, dtype=np.int32)
+        degrees = np.ascontiguousarray(degrees, dtype=np.int32)
+        out = np.empty(2 * len(rows))
+        _check(_lib.jt_plan_entries(self._h, axis, len(rows), rows.ctypes.data_as(_ip),
+                                    degrees.ctypes.data_as(_ip), _dptr(out)))
+        return out.view(np.complex128)
+
+    def device_bytes(self) -> int:
+        b = ctypes.c_size_t()
+        _check(_lib.jt_plan_device_bytes(self._h, ctypes.byref(b)))
+        return b.value
+
+    # ------------------------------------------------------------ device side
+    def bind(self, device=None, stream=None):
+        """Allocate the factor buffer with torch on `device` and copy the factors in."""
+        import torch
+
+        device = torch.device(device or "cuda")
+        nbytes = self.device_bytes()
+        buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        off = (-buf.data_ptr()) % 256
+        self._dev = buf
+        self._dev_off = off
+        st = stream if stream is not None else torch.cuda.current_stream(device)
+        _check(_lib.jt_plan_bind(self._h, _vp(buf.data_ptr() + off), nbytes, _vp(st.cuda_stream)))
+        return self
+
+    @staticmethod
+    def _dtype_code(t) -> int:
+        import torch
+
+        if t.dtype == torch.float64:
+            return F64
+        if t.dtype == torch.float32:
+            return F32
+        raise TypeError("tensors must be float32 or float64")
+
+    def _check_tensor(self, t):
+        import torch
+
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError("expected a CUDA (HIP) torch tensor")
+        if tuple(t.shape) != self.n or not t.is_contiguous():
+            raise ValueError("expected a contiguous tensor of shape %r, got %r" % (self.n, tuple(t.shape)))
+
+    def _run(self, fn, x, out, prec, stream):
+        import torch
+
+        if self._dev is None:
+            raise JTError(JT_ESTATE, "plan is not bound; call bind()")
+        self._check_tensor(x)
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.float64, device=x.device)
+        self._check_tensor(out)
+        st = stream if stream is not None else torch.cuda.current_stream(x.device)
+        _check(fn(self._h, _vp(x.data_ptr()), self._dtype_code(x), _vp(out.data_ptr()),
+                  self._dtype_code(out), int(prec), _vp(st.cuda_stream)))
+        return out
+
+    def forward(self, alpha, out=None, prec: int = PREC_FP64, stream=None):
+        """g = (W0 J0 (x) ...) alpha, on the GPU."""
+        return self._run(_lib.jt_forward, alpha, out, prec, stream)
+
+    def inverse(self, g, out=None, prec: int = PREC_FP64, stream=None):
+        """alpha = (W0 J0 (x) ...)^T g, on the GPU."""
+        return self._run(_lib.jt_inverse, g, out, prec, stream)
+
+    def apply_axis(self, axis: int, direction: int, x, out=None, prec: int = PREC_FP64, stream=None):
+        import torch
+
+        if self._dev is None:
+            raise JTError(JT_ESTATE, "plan is not bound; call bind()")
+        self._check_tensor(x)
+        if out is None:
+            out = torch.empty(self.n, dtype=x.dtype, device=x.device)
+        self._check_tensor(out)
+        st = stream if stream is not None else torch.cuda.current_stream(x.device)
+        _check(_lib.jt_apply_axis(self._h, axis, direction, _vp(x.data_ptr()), self._dtype_code(x),
+                                  _vp(out.data_ptr()), self._dtype_code(out), int(prec),
+                                  _vp(st.cuda_stream)))
+        return out

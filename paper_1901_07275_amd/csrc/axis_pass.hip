@@ -1,0 +1,490 @@
+// Fused axis-pass kernels for the fast uniform Jacobi transform on gfx950.
+//
+// One pass applies W J_n^(a,b) (forward) or its transpose (inverse) along one
+// axis of a row-major tensor, independently on every line (Section 3.1 for a
+// single line; Sections 3.2-3.3 apply it axis by axis, eqs. (54)-(55),
+// (59)-(60)).  Per line, the forward pass computes eq. (50):
+//
+//   out_j = sum_{k<nu0} (WV)_{jk} alpha_k
+//         + Re sum_l u_{l,j} * y_l[m_j],   y_l[m] = sum_k v_{l,k} alpha_k e^{+2 pi i m k / L}
+//
+// and the inverse pass computes eq. (51):
+//
+//   alpha_k = sum_j (WV)_{jk} g_j                       (k < nu0)
+//   alpha_k = Re sum_l v_{l,k} * Y_l[k],  Y_l[k] = sum_m e^{+2 pi i m k / L} z_l[m],
+//             z_l[m] = sum_{j : m_j = m} u_{l,j} g_j     (k >= nu0)
+//
+// Layout of a line inside the kernel: P = L/16 lanes per line, lane p holds
+// the 16 elements p + P*q (q = 0..15) in registers.  The L-point DFT is a
+// Stockham radix-16 FFT (with one final radix-2/4/8 pass when log2 L is not a
+// multiple of 4): the first pass starts from registers (no LDS read), the
+// last pass ends in registers in the same lane-owned layout, and the passes
+// in between exchange through a padded LDS line buffer.  The gather of
+// y[m_j] (forward) and the bin sums of z (inverse) also go through that
+// buffer.  The rank sum is accumulated in fp64 in both precisions.
+#include <hip/hip_runtime.h>
+
+#include "launch.h"
+
+namespace jt {
+namespace {
+
+template <class T>
+struct cpx {
+    T x, y;
+};
+
+template <class T>
+__device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <class T>
+__device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <class T>
+__device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b)
+{
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <class T>
+__device__ __forceinline__ cpx<T> muli(cpx<T> a) { return {-a.y, a.x}; }
+
+// exp(2 pi i e / 16) for e = 0..15
+constexpr double kW16c[16] = {
+    1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+    0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+    -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173,
+    0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613};
+constexpr double kW16s[16] = {
+    0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613,
+    1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+    0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+    -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173};
+
+template <class T, int E>
+__device__ __forceinline__ cpx<T> w16(cpx<T> a)
+{
+    constexpr int e = E & 15;
+    if constexpr (e == 0) {
+        return a;
+    } else if constexpr (e == 4) {
+        return {-a.y, a.x};
+    } else if constexpr (e == 8) {
+        return {-a.x, -a.y};
+    } else if constexpr (e == 12) {
+        return {a.y, -a.x};
+    } else if constexpr (e == 2 || e == 6 || e == 10 || e == 14) {
+        // (c, s) with |c| = |s| = sqrt(2)/2
+        constexpr T r = (T)0.70710678118654752440;
+        constexpr T cs = (e == 2 || e == 14) ? r : -r;
+        constexpr T sn = (e == 2 || e == 6) ? r : -r;
+        return {cs * a.x - sn * a.y, sn * a.x + cs * a.y};
+    } else {
+        constexpr T c = (T)kW16c[e], s = (T)kW16s[e];
+        return {c * a.x - s * a.y, s * a.x + c * a.y};
+    }
+}
+
+template <class T>
+__device__ __forceinline__ void dft2(cpx<T> &a0, cpx<T> &a1)
+{
+    cpx<T> t = a0;
+    a0 = t + a1;
+    a1 = t - a1;
+}
+
+// sign +:  X_m = sum_k a_k i^{k m}
+template <class T>
+__device__ __forceinline__ void dft4(cpx<T> &a0, cpx<T> &a1, cpx<T> &a2, cpx<T> &a3)
+{
+    cpx<T> t0 = a0 + a2, t1 = a0 - a2, t2 = a1 + a3, t3 = muli(a1 - a3);
+    a0 = t0 + t2;
+    a2 = t0 - t2;
+    a1 = t1 + t3;
+    a3 = t1 - t3;
+}
+
+// In-place 8-point DFT (sign +), natural order in and out: 8 = 2 x 4.
+template <class T>
+__device__ __forceinline__ void dft8(cpx<T> *v)
+{
+    // k = k1 + 2 k2:  4-point DFTs over k2 for k1 = 0, 1
+    dft4(v[0], v[2], v[4], v[6]);
+    dft4(v[1], v[3], v[5], v[7]);
+    // twiddle omega_8^{k1 m2} = omega_16^{2 k1 m2}
+    v[3] = w16<T, 2>(v[3]);
+    v[5] = w16<T, 4>(v[5]);
+    v[7] = w16<T, 6>(v[7]);
+    // X[m2 + 4 m1] = 2-point DFT over k1 of Y[k1][m2] (stored at v[k1 + 2 m2])
+    cpx<T> o[8];
+#pragma unroll
+    for (int m2 = 0; m2 < 4; ++m2) {
+        cpx<T> a = v[2 * m2], b = v[2 * m2 + 1];
+        o[m2] = a + b;
+        o[m2 + 4] = a - b;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = o[i];
+}
+
+// In-place 16-point DFT (sign +), natural order in and out: 16 = 4 x 4.
+template <class T>
+__device__ __forceinline__ void dft16(cpx<T> *v)
+{
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) dft4(v[k1], v[k1 + 4], v[k1 + 8], v[k1 + 12]);
+    v[5] = w16<T, 1>(v[5]);
+    v[9] = w16<T, 2>(v[9]);
+    v[13] = w16<T, 3>(v[13]);
+    v[6] = w16<T, 2>(v[6]);
+    v[10] = w16<T, 4>(v[10]);
+    v[14] = w16<T, 6>(v[14]);
+    v[7] = w16<T, 3>(v[7]);
+    v[11] = w16<T, 6>(v[11]);
+    v[15] = w16<T, 9>(v[15]);
+    cpx<T> o[16];
+#pragma unroll
+    for (int m2 = 0; m2 < 4; ++m2) {
+        cpx<T> a0 = v[4 * m2], a1 = v[4 * m2 + 1], a2 = v[4 * m2 + 2], a3 = v[4 * m2 + 3];
+        dft4(a0, a1, a2, a3);
+        o[m2] = a0;
+        o[m2 + 4] = a1;
+        o[m2 + 8] = a2;
+        o[m2 + 12] = a3;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = o[i];
+}
+
+template <class T, int R>
+__device__ __forceinline__ void dftR(cpx<T> *v)
+{
+    if constexpr (R == 2) dft2(v[0], v[1]);
+    else if constexpr (R == 4) dft4(v[0], v[1], v[2], v[3]);
+    else if constexpr (R == 8) dft8(v);
+    else dft16(v);
+}
+
+// padded LDS index: one spare slot every 16 elements
+__device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
+
+template <int LOG2L>
+struct Geo {
+    static constexpr int L = 1 << LOG2L;
+    static constexpr int P = L / 16;                 // lanes per line
+    static constexpr int S16 = LOG2L / 4;            // radix-16 passes
+    static constexpr int F = LOG2L % 4;
+    static constexpr int RF = 1 << F;                // final radix (1: none)
+    static constexpr int NMID = S16 - 1;             // radix-16 passes after the first
+    static constexpr int BLOCK = (P < 64) ? 64 : P;  // threads per block
+    static constexpr int LPB = BLOCK / P;            // lines per block
+    static constexpr int BUF = L + L / 16;           // padded line buffer (complex)
+};
+
+// Lane-constant twiddles of all passes after the first.  Small blocks keep
+// them in registers for the whole kernel; blocks of 512+ threads (L >= 8192)
+// have too few registers per lane and read them from the table when used.
+template <class T, int LOG2L>
+struct Twiddles {
+    using G = Geo<LOG2L>;
+    static constexpr bool kHoist = G::BLOCK <= 256;
+    cpx<T> mid_[(kHoist && G::NMID > 0) ? G::NMID : 1][15];
+    cpx<T> fin_[(kHoist && G::RF > 1) ? 16 / G::RF : 1][(G::RF > 1) ? G::RF - 1 : 1];
+    const cpx<T> *tw;
+    int p;
+
+    // pass i+1 has Ns = 16^(i+1); factor omega_{16 Ns}^{(p mod Ns) r} = tw[(p mod Ns) r L / (16 Ns)]
+    static __device__ __forceinline__ int mid_index(int i, int r, int p)
+    {
+        int ns = 16;
+        for (int k = 0; k < i; ++k) ns *= 16;
+        return (p % ns) * r * (G::L / (16 * ns));
+    }
+    // final pass (radix RF, Ns = L/RF): task j = p + P t, factor omega_L^{j r}
+    static __device__ __forceinline__ int fin_index(int t, int r, int p) { return (p + G::P * t) * r; }
+
+    __device__ __forceinline__ void load(const cpx<T> *table, int lane)
+    {
+        tw = table;
+        p = lane;
+        if constexpr (kHoist) {
+#pragma unroll
+            for (int i = 0; i < G::NMID; ++i)
+#pragma unroll
+                for (int r = 1; r < 16; ++r) mid_[i][r - 1] = tw[mid_index(i, r, p)];
+            if constexpr (G::RF > 1) {
+#pragma unroll
+                for (int t = 0; t < 16 / G::RF; ++t)
+#pragma unroll
+                    for (int r = 1; r < G::RF; ++r) fin_[t][r - 1] = tw[fin_index(t, r, p)];
+            }
+        }
+    }
+    __device__ __forceinline__ cpx<T> mid(int i, int r) const
+    {
+        if constexpr (kHoist) return mid_[i][r - 1];
+        else return tw[mid_index(i, r, p)];
+    }
+    __device__ __forceinline__ cpx<T> fin(int t, int r) const
+    {
+        if constexpr (kHoist) return fin_[t][r - 1];
+        else return tw[fin_index(t, r, p)];
+    }
+};
+
+// L-point DFT (sign +) of the line held in v (lane-owned layout, v[q] = x[p + P q]);
+// on return v[q] = X[p + P q].  buf is this line's LDS buffer.  Every thread of
+// the block must call it (it contains block barriers).
+template <class T, int LOG2L>
+__device__ __forceinline__ void fft_line(cpx<T> *v, cpx<T> *buf, int p, const Twiddles<T, LOG2L> &tw)
+{
+    using G = Geo<LOG2L>;
+    // pass 0: Ns = 1, no twiddles, inputs are already v[r] = x[p + r P]
+    dft16(v);
+    if constexpr (G::S16 == 1 && G::RF == 1) {
+        return;  // L = 16 (not instantiated)
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) buf[pad(p * 16 + r)] = v[r];
+    int ns = 16;
+#pragma unroll
+    for (int i = 0; i < G::NMID; ++i) {
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = buf[pad(p + r * G::P)];
+#pragma unroll
+        for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], tw.mid(i, r));
+        dft16(v);
+        const bool last = (G::RF == 1) && (i == G::NMID - 1);
+        if (!last) {
+            __syncthreads();
+            const int base = (p / ns) * ns * 16 + (p % ns);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) buf[pad(base + r * ns)] = v[r];
+        }
+        ns *= 16;
+    }
+    if constexpr (G::RF > 1) {
+        constexpr int RF = G::RF, NT = 16 / RF;
+        __syncthreads();
+        cpx<T> w[16];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int j = p + G::P * t;
+#pragma unroll
+            for (int r = 0; r < RF; ++r) w[t * RF + r] = buf[pad(j + r * (G::L / RF))];
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+#pragma unroll
+            for (int r = 1; r < RF; ++r) w[t * RF + r] = cmul(w[t * RF + r], tw.fin(t, r));
+            dftR<T, RF>(&w[t * RF]);
+            // output index j + r * (L/RF) = p + P (t + r * NT)
+#pragma unroll
+            for (int r = 0; r < RF; ++r) v[t + r * NT] = w[t * RF + r];
+        }
+    }
+}
+
+template <class T>
+__device__ __forceinline__ T load_elem(const void *p, long long i, int f64)
+{
+    return f64 ? (T)((const double *)p)[i] : (T)((const float *)p)[i];
+}
+__device__ __forceinline__ void store_elem(void *p, long long i, int f64, double v)
+{
+    if (f64) ((double *)p)[i] = v;
+    else ((float *)p)[i] = (float)v;
+}
+
+// Blocks that share an XCD get neighbouring lines, so that the strided passes
+// reuse cache lines within one L2.
+__device__ __forceinline__ long long block_line(long long lpb)
+{
+    const unsigned b = blockIdx.x, g = gridDim.x;
+    unsigned lb = b;
+    if ((g & 7u) == 0u) lb = (b & 7u) * (g >> 3) + (b >> 3);
+    return (long long)lb * lpb;
+}
+
+template <class T, int LOG2L, int FWD>
+__global__ void __launch_bounds__(Geo<LOG2L>::BLOCK) axis_pass(AxisLaunch a)
+{
+    using G = Geo<LOG2L>;
+    __shared__ cpx<T> smem[G::LPB * G::BUF];
+    const int slot = threadIdx.x / G::P;
+    const int p = threadIdx.x % G::P;
+    cpx<T> *buf = smem + slot * G::BUF;
+    T *sbuf = reinterpret_cast<T *>(buf);
+
+    const long long line = block_line(G::LPB) + slot;
+    const bool active = line < a.lines;
+    const long long outer = active ? line / a.stride : 0;
+    const long long inner = active ? line % a.stride : 0;
+    const long long base = outer * (long long)a.n * a.stride + inner;
+    const int n = a.n, nu0 = a.nu0;
+
+    const cpx<T> *tw = reinterpret_cast<const cpx<T> *>(a.tw);
+    const cpx<T> *uf = reinterpret_cast<const cpx<T> *>(a.u);
+    const cpx<T> *vf = reinterpret_cast<const cpx<T> *>(a.v);
+    const T *wv = reinterpret_cast<const T *>(a.wv);
+    const T *wvt = reinterpret_cast<const T *>(a.wvt);
+
+    Twiddles<T, LOG2L> twd;
+    twd.load(tw, p);
+
+    T x[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int k = p + G::P * q;
+        x[q] = (active && k < n) ? load_elem<T>(a.in, base + (long long)k * a.stride, a.in_f64) : (T)0;
+    }
+    double acc[16];
+
+    if constexpr (FWD) {
+        // ---- direct block: out_j = sum_{k<nu0} WV[k][j] alpha_k (alpha_k broadcast via LDS)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int k = p + G::P * q;
+            if (k < nu0) sbuf[k] = x[q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int j = p + G::P * q;
+            T s = 0;
+            if (j < n)
+                for (int k = 0; k < nu0; ++k) s += wv[(long long)k * n + j] * sbuf[k];
+            acc[q] = (double)s;
+        }
+        int mb[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int j = p + G::P * q;
+            mb[q] = (j < n) ? a.bins[j] : 0;
+        }
+        for (int l = 0; l < a.rank; ++l) {
+            cpx<T> v[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const cpx<T> f = vf[(long long)l * G::L + p + G::P * q];
+                v[q] = {f.x * x[q], f.y * x[q]};
+            }
+            __syncthreads();  // previous users of buf are done
+            fft_line<T, LOG2L>(v, buf, p, twd);
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int m = p + G::P * q;
+                if (m <= G::L / 2) buf[pad(m)] = v[q];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int j = p + G::P * q;
+                if (j < n) {
+                    const cpx<T> y = buf[pad(mb[q])];
+                    const cpx<T> u = uf[(long long)l * n + j];
+                    acc[q] += (double)(u.x * y.x - u.y * y.y);
+                }
+            }
+        }
+    } else {
+        // ---- direct block: alpha_k = sum_j WV[k][j] g_j for k < nu0 (g broadcast via LDS)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int j = p + G::P * q;
+            if (j < n) sbuf[j] = x[q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int k = p + G::P * q;
+            T s = 0;
+            if (k < nu0)
+                for (int j = 0; j < n; ++j) s += wvt[(long long)j * nu0 + k] * sbuf[j];
+            acc[q] = (double)s;
+        }
+        int b0[16], b1[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int m = p + G::P * q;
+            b0[q] = (m <= G::L / 2) ? a.binptr[m] : 0;
+            b1[q] = (m <= G::L / 2) ? a.binptr[m + 1] : 0;
+        }
+        for (int l = 0; l < a.rank; ++l) {
+            __syncthreads();  // previous users of buf are done
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int j = p + G::P * q;
+                if (j < n) {
+                    const cpx<T> u = uf[(long long)l * n + j];
+                    buf[pad(j)] = {u.x * x[q], u.y * x[q]};
+                }
+            }
+            __syncthreads();
+            cpx<T> v[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                cpx<T> z = {(T)0, (T)0};
+                for (int jj = b0[q]; jj < b1[q]; ++jj) z = z + buf[pad(jj)];
+                v[q] = z;
+            }
+            __syncthreads();
+            fft_line<T, LOG2L>(v, buf, p, twd);
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int k = p + G::P * q;
+                const cpx<T> f = vf[(long long)l * G::L + k];
+                acc[q] += (double)(f.x * v[q].x - f.y * v[q].y);
+            }
+        }
+    }
+    // all reads of the input happened before the first barrier, so the
+    // output may alias the input (in-place passes)
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int i = p + G::P * q;
+        if (active && i < n) store_elem(a.out, base + (long long)i * a.stride, a.out_f64, acc[q]);
+    }
+}
+
+template <class T, int LOG2L>
+hipError_t launch_t(const AxisLaunch &a, hipStream_t s)
+{
+    using G = Geo<LOG2L>;
+    const long long blocks = (a.lines + G::LPB - 1) / G::LPB;
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    if (a.forward)
+        hipLaunchKernelGGL((axis_pass<T, LOG2L, 1>), dim3((unsigned)blocks), dim3(G::BLOCK), 0, s, a);
+    else
+        hipLaunchKernelGGL((axis_pass<T, LOG2L, 0>), dim3((unsigned)blocks), dim3(G::BLOCK), 0, s, a);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_prec(const AxisLaunch &a, hipStream_t s)
+{
+    switch (a.L) {
+    case 64: return launch_t<T, 6>(a, s);
+    case 128: return launch_t<T, 7>(a, s);
+    case 256: return launch_t<T, 8>(a, s);
+    case 512: return launch_t<T, 9>(a, s);
+    case 1024: return launch_t<T, 10>(a, s);
+    case 2048: return launch_t<T, 11>(a, s);
+    case 4096: return launch_t<T, 12>(a, s);
+    case 8192: return launch_t<T, 13>(a, s);
+    default: break;
+    }
+    if constexpr (sizeof(T) == 4) {
+        if (a.L == 16384) return launch_t<T, 14>(a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_axis(const AxisLaunch &a, hipStream_t stream)
+{
+    return a.fp32 ? launch_prec<float>(a, stream) : launch_prec<double>(a, stream);
+}
+
+}  // namespace jt

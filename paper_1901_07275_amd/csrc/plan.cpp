@@ -1,0 +1,698 @@
+// Host plan: nodes, weights, bins, direct block, companion function and the
+// randomized low-rank factorization of W B_n (Section 2.1, Section 3.1).
+#include "plan.h"
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <stdexcept>
+#include <thread>
+
+#include "dense.h"
+
+namespace jt {
+
+typedef long double ld;
+static const ld kPi = 3.141592653589793238462643383279502884L;
+
+// ------------------------------------------------------------------ threads
+template <class F>
+static void parallel_for(int count, F f)
+{
+    unsigned hw = std::thread::hardware_concurrency();
+    int nt = (int)std::min<unsigned>(hw ? hw : 1, 16);
+    if (count < 64 || nt <= 1) {
+        for (int i = 0; i < count; ++i) f(i);
+        return;
+    }
+    std::atomic<int> next(0);
+    auto work = [&]() {
+        for (;;) {
+            int i0 = next.fetch_add(16);
+            if (i0 >= count) break;
+            int i1 = std::min(count, i0 + 16);
+            for (int i = i0; i < i1; ++i) f(i);
+        }
+    };
+    std::vector<std::thread> th;
+    for (int k = 1; k < nt; ++k) th.emplace_back(work);
+    work();
+    for (auto &t : th) t.join();
+}
+
+// ------------------------------------------------------------------ RNG
+// splitmix64: counter-based, so plans are reproducible for a given key.
+struct Rng {
+    uint64_t s;
+    explicit Rng(uint64_t seed) : s(seed) {}
+    uint64_t next()
+    {
+        uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    }
+    int below(int m) { return (int)(next() % (uint64_t)m); }
+};
+
+static uint64_t mix_key(int n, double a, double b, double tol)
+{
+    uint64_t h = 0x243F6A8885A308D3ull ^ (uint64_t)n;
+    double v[3] = {a, b, tol};
+    for (double d : v) {
+        uint64_t u;
+        std::memcpy(&u, &d, 8);
+        Rng r(h ^ u);
+        h = r.next();
+    }
+    return h ? h : 1;
+}
+
+// k distinct indices from [0, m) that are not in `excl`, sorted.
+static std::vector<int> sample(Rng &rng, int m, int k, const std::vector<int> &excl)
+{
+    std::vector<char> taken(m, 0);
+    for (int e : excl) taken[e] = 1;
+    std::vector<int> pool;
+    pool.reserve(m);
+    for (int i = 0; i < m; ++i)
+        if (!taken[i]) pool.push_back(i);
+    k = std::min<int>(k, (int)pool.size());
+    for (int i = 0; i < k; ++i) {
+        int j = i + rng.below((int)pool.size() - i);
+        std::swap(pool[i], pool[j]);
+    }
+    std::vector<int> out(pool.begin(), pool.begin() + k);
+    std::sort(out.begin(), out.end());
+    return out;
+}
+
+static std::vector<int> merged(const std::vector<int> &x, const std::vector<int> &y)
+{
+    std::vector<int> z(x);
+    z.insert(z.end(), y.begin(), y.end());
+    std::sort(z.begin(), z.end());
+    z.erase(std::unique(z.begin(), z.end()), z.end());
+    return z;
+}
+
+// ------------------------------------------------------------------ recurrence
+// Orthonormal Jacobi polynomials for w(x) = (1-x)^a (1+x)^b:
+//   x p_k = be[k+1] p_{k+1} + al[k] p_k + be[k] p_{k-1},  p_0 = mu0^{-1/2}.
+struct Rec {
+    std::vector<ld> al, be;
+    ld mu0 = 0, sqrt_mu0 = 0;
+};
+
+static Rec recurrence(int N, ld a, ld b)
+{
+    Rec r;
+    r.al.resize(N + 1);
+    r.be.resize(N + 2);
+    const ld ab = a + b;
+    for (int k = 0; k <= N; ++k) {
+        if (k == 0) {
+            r.al[k] = (b - a) / (ab + 2);
+        } else {
+            ld s = 2 * (ld)k + ab;
+            r.al[k] = (b - a) * (b + a) / (s * (s + 2));
+        }
+    }
+    r.be[0] = 0;
+    for (int k = 1; k <= N + 1; ++k) {
+        if (k == 1) {
+            r.be[1] = sqrtl(4 * (1 + a) * (1 + b) / ((ab + 2) * (ab + 2) * (ab + 3)));
+        } else {
+            ld s = 2 * (ld)k + ab;
+            r.be[k] = sqrtl(4 * (ld)k * (k + a) * (k + b) * (k + ab) / (s * s * (s + 1) * (s - 1)));
+        }
+    }
+    r.mu0 = expl((ab + 1) * logl(2.0L) + lgammal(a + 1) + lgammal(b + 1) - lgammal(ab + 2));
+    r.sqrt_mu0 = sqrtl(r.mu0);
+    return r;
+}
+
+// p_n(x), p_{n-1}(x), p_n'(x) and p_{n-1}'(x).
+static void eval_top(const Rec &r, int n, ld x, ld &pn, ld &pn1, ld &dpn, ld *dpn1 = nullptr)
+{
+    ld pm = 0, p = 1 / r.sqrt_mu0, dm = 0, d = 0;
+    for (int k = 0; k < n; ++k) {
+        ld ip = 1 / r.be[k + 1];
+        ld pnew = ((x - r.al[k]) * p - r.be[k] * pm) * ip;
+        ld dnew = ((x - r.al[k]) * d + p - r.be[k] * dm) * ip;
+        pm = p; p = pnew;
+        dm = d; d = dnew;
+    }
+    pn = p; pn1 = pm; dpn = d;
+    if (dpn1) *dpn1 = dm;
+}
+
+// Gauss-Jacobi weight at (an approximation of) a zero of p_n, from the
+// Christoffel-Darboux identity  sum_{k<n} p_k^2 = be_n (p_n' p_{n-1} - p_{n-1}' p_n).
+// Keeping the second term makes the result insensitive to the last-bit
+// error of the zero itself (important near x = +-1, where x = cos t cannot
+// resolve the root finer than its own rounding).
+static ld weight_at(const Rec &r, int n, ld x)
+{
+    ld pn, pn1, dpn, dpn1;
+    eval_top(r, n, x, pn, pn1, dpn, &dpn1);
+    return 1 / (r.be[n] * (dpn * pn1 - dpn1 * pn));
+}
+
+// ------------------------------------------------------------------ nodes
+// Newton iteration in t on p_n(cos t) from the interior asymptotic zeros
+// t_j ~ (j + a/2 - 1/4) pi / (n + (a+b+1)/2); a sign-change scan is the
+// fallback when the Newton roots are not n distinct increasing values.
+static bool newton_root(const Rec &r, int n, ld &t, ld lo, ld hi)
+{
+    int extra = -1;
+    for (int it = 0; it < 60; ++it) {
+        ld pn, pn1, dpn;
+        eval_top(r, n, cosl(t), pn, pn1, dpn);
+        ld fp = -sinl(t) * dpn;
+        if (fp == 0) return false;
+        ld step = pn / fp;
+        ld tn = t - step;
+        if (!(tn > lo && tn < hi)) tn = (tn <= lo) ? 0.5L * (t + lo) : 0.5L * (t + hi);
+        t = tn;
+        if (extra < 0 && fabsl(step) < 1e-14L) extra = 2;
+        if (extra >= 0 && extra-- == 0) return true;
+    }
+    return false;
+}
+
+static void nodes_ld(const Rec &r, int n, ld a, ld b, std::vector<ld> &t)
+{
+    t.assign(n, 0);
+    const ld N = n + (a + b + 1) / 2;
+    const ld cell = kPi / N;
+    std::atomic<int> bad(0);
+    parallel_for(n, [&](int j) {
+        ld tj = (j + 1 + a / 2 - 0.25L) * cell;
+        ld lo = std::max<ld>(0, tj - cell), hi = std::min<ld>(kPi, tj + cell);
+        if (tj <= lo || tj >= hi) tj = 0.5L * (lo + hi);
+        if (!newton_root(r, n, tj, lo, hi)) bad.fetch_add(1);
+        t[j] = tj;
+    });
+    bool ok = bad.load() == 0;
+    for (int j = 0; ok && j < n; ++j) {
+        if (!(t[j] > 0 && t[j] < kPi)) ok = false;
+        if (j && !(t[j] > t[j - 1] + 1e-6L * cell)) ok = false;
+    }
+    if (ok) return;
+    // fallback: bracket every root by sign changes on a fine grid in t
+    const int M = 32 * n + 64;
+    std::vector<ld> tg(M), fg(M);
+    parallel_for(M, [&](int i) {
+        tg[i] = kPi * (i + 0.5L) / M;
+        ld pn, pn1, dpn;
+        eval_top(r, n, cosl(tg[i]), pn, pn1, dpn);
+        fg[i] = pn;
+    });
+    std::vector<std::pair<ld, ld>> br;
+    for (int i = 0; i + 1 < M; ++i)
+        if ((fg[i] < 0) != (fg[i + 1] < 0)) br.push_back({tg[i], tg[i + 1]});
+    if ((int)br.size() != n) throw std::runtime_error("Gauss-Jacobi node search did not isolate n roots");
+    parallel_for(n, [&](int j) {
+        ld lo = br[j].first, hi = br[j].second;
+        ld tj = 0.5L * (lo + hi);
+        // bisection to a small bracket, then Newton
+        for (int it = 0; it < 40; ++it) {
+            ld pl, p1, d;
+            eval_top(r, n, cosl(lo), pl, p1, d);
+            ld pm, q1, e;
+            eval_top(r, n, cosl(tj), pm, q1, e);
+            if ((pl < 0) != (pm < 0)) hi = tj; else lo = tj;
+            tj = 0.5L * (lo + hi);
+            if (hi - lo < 1e-9L * cell) break;
+        }
+        if (!newton_root(r, n, tj, lo - cell * 1e-6L, hi + cell * 1e-6L)) bad.fetch_add(1);
+        t[j] = tj;
+    });
+}
+
+void gauss_jacobi(int n, double a, double b, std::vector<double> &t, std::vector<double> &x,
+                  std::vector<double> &omega)
+{
+    Rec r = recurrence(n, a, b);
+    std::vector<ld> tl;
+    nodes_ld(r, n, a, b, tl);
+    t.resize(n); x.resize(n); omega.resize(n);
+    for (int j = 0; j < n; ++j) {
+        ld xj = cosl(tl[j]);
+        ld om = weight_at(r, n, xj);
+        t[j] = (double)tl[j];
+        x[j] = (double)xj;
+        omega[j] = (double)om;
+    }
+}
+
+// ------------------------------------------------------------------ companion
+// H(x) = PV int (1-s)^a (1+s)^b / (s - x) ds
+//      = w(x) log((1-x)/(1+x)) + int_{-1}^{1} (w(s) - w(x)) / (s - x) ds.
+// The smooth remainder is split at s = x into two halves.  On each half, with
+// v = |s - x|, the integrand is  +-w(x) expm1(Lambda(v)) / v  where Lambda is
+// the log of w(s)/w(x) written with log1p so it stays accurate for small v.
+// Each half has a power singularity at its far end (+-1) and a nearby one just
+// beyond x at distance delta (the other endpoint); it is cut into geometric
+// pieces d_{i+1} = 2 d_i + delta graded away from x (Gauss-Legendre 16 on each)
+// and a final tanh-sinh piece that reaches the far endpoint.
+namespace {
+struct QuadTables {
+    ld gl_x[16], gl_w[16];
+    std::vector<ld> ts_tau, ts_ctau, ts_w;  // tanh-sinh: tau, 1 - tau, weight
+    QuadTables()
+    {
+        Rec r = recurrence(16, 0, 0);
+        std::vector<ld> tl;
+        nodes_ld(r, 16, 0, 0, tl);
+        for (int j = 0; j < 16; ++j) {
+            ld xj = cosl(tl[j]);
+            gl_x[j] = xj;
+            gl_w[j] = weight_at(r, 16, xj);  // Gauss-Legendre weights on [-1, 1]
+        }
+        const ld h = 1.0L / 16;
+        const int K = 64;
+        for (int k = -K; k <= K; ++k) {
+            ld y = k * h;
+            ld yp = kPi / 2 * sinhl(y);
+            ld tau = 1 / (1 + expl(-2 * yp));
+            ld ctau = 1 / (1 + expl(2 * yp));
+            ld w = h * kPi * coshl(y) * tau * ctau;
+            ts_tau.push_back(tau);
+            ts_ctau.push_back(ctau);
+            ts_w.push_back(w);
+        }
+    }
+};
+const QuadTables &quad_tables()
+{
+    static QuadTables t;
+    return t;
+}
+
+// integral over v in [0, ell] of expm1(e_far*log((ell-v)/ell) + e_near*log1p(v/delta)) / v
+ld half_integral(ld e_far, ld e_near, ld ell, ld delta)
+{
+    const QuadTables &T = quad_tables();
+    auto phi = [&](ld v, ld ellmv) -> ld {
+        ld lf = (v < 0.5L * ell) ? log1pl(-v / ell) : logl(ellmv / ell);
+        ld lam = e_far * lf + e_near * log1pl(v / delta);
+        return expm1l(lam) / v;
+    };
+    ld sum = 0;
+    ld d = 0;
+    for (;;) {
+        ld nxt = 2 * d + delta;
+        if (nxt > 0.5L * ell) break;
+        ld c = 0.5L * (d + nxt), h = 0.5L * (nxt - d);
+        for (int i = 0; i < 16; ++i) {
+            ld v = c + h * T.gl_x[i];
+            sum += h * T.gl_w[i] * phi(v, ell - v);
+        }
+        d = nxt;
+    }
+    const ld len = ell - d;
+    for (size_t k = 0; k < T.ts_tau.size(); ++k) {
+        ld v = d + len * T.ts_tau[k];
+        ld ellmv = len * T.ts_ctau[k];
+        if (!(v > 0) || !(ellmv > 0)) continue;
+        sum += len * T.ts_w[k] * phi(v, ellmv);
+    }
+    return sum;
+}
+
+ld hilbert_weight_parts(ld omx, ld opx, ld a, ld b)
+{
+    ld wx = powl(omx, a) * powl(opx, b);
+    ld right = half_integral(a, b, omx, opx);
+    ld left = half_integral(b, a, opx, omx);
+    return wx * (logl(omx / opx) + right - left);
+}
+}  // namespace
+
+long double hilbert_weight(long double x, long double a, long double b)
+{
+    return hilbert_weight_parts(1 - x, 1 + x, a, b);
+}
+
+// ------------------------------------------------------------------ matrix W B
+namespace {
+struct Evaluator {
+    int n = 0, nu0 = 0, L = 0, Nc = 0;
+    Rec rec;
+    std::vector<ld> x, sw, invpw, q0;  // node, sqrt(omega), 1/(pi w(x)), q_0(x)
+    std::vector<int> m;
+    std::vector<cd> ph;  // ph[p] = exp(-2 pi i p / L)
+
+    // Walk the p and q recurrences at node j up to degree kmax, calling
+    // emit(k, p_k, q_k) for every k.
+    template <class F>
+    void walk(int j, int kmax, F emit) const
+    {
+        const ld xj = x[j];
+        ld pm = 0, p = 1 / rec.sqrt_mu0, qm = 0, q = q0[j];
+        for (int k = 0; k <= kmax; ++k) {
+            emit(k, p, q);
+            if (k == kmax) break;
+            ld ib = 1 / rec.be[k + 1];
+            ld pn = ((xj - rec.al[k]) * p - rec.be[k] * pm) * ib;
+            ld qn = ((xj - rec.al[k]) * q - rec.be[k] * qm + (k == 0 ? rec.sqrt_mu0 : 0)) * ib;
+            pm = p; p = pn;
+            qm = q; q = qn;
+        }
+    }
+    cd entry(int j, int k, ld p, ld q) const
+    {
+        int64_t e = ((int64_t)m[j] * k) % L;
+        cd z((double)(sw[j] * p), (double)(sw[j] * q * invpw[j]));
+        return z * ph[e];
+    }
+    void row(int j, cd *out) const
+    {
+        walk(j, n - 1, [&](int k, ld p, ld q) {
+            if (k >= nu0) out[k - nu0] = entry(j, k, p, q);
+        });
+    }
+    // columns (degree offsets c = k - nu0), sorted ascending
+    CMat cols(const std::vector<int> &cs) const
+    {
+        CMat out(n, (int)cs.size());
+        if (cs.empty()) return out;
+        int kmax = nu0 + cs.back();
+        parallel_for(n, [&](int j) {
+            size_t ci = 0;
+            walk(j, kmax, [&](int k, ld p, ld q) {
+                while (ci < cs.size() && nu0 + cs[ci] == k) {
+                    out(j, (int)ci) = entry(j, k, p, q);
+                    ++ci;
+                }
+            });
+        });
+        return out;
+    }
+    CMat rows(const std::vector<int> &rs) const
+    {
+        CMat out((int)rs.size(), Nc);
+        parallel_for((int)rs.size(), [&](int i) {
+            std::vector<cd> r(Nc);
+            row(rs[i], r.data());
+            for (int c = 0; c < Nc; ++c) out(i, c) = r[c];
+        });
+        return out;
+    }
+};
+}  // namespace
+
+static void rsvd(const Evaluator &E, double tol, const PlanOptions &opt, uint64_t seed, AxisPlan &ax)
+{
+    const int Nr = E.n, Nc = E.Nc;
+    const int rmax = std::min(Nr, Nc);
+    int r = std::min(rmax, std::max(4, (int)std::ceil(2.0 * std::log2((double)E.n))));
+    Rng rng(seed);
+    const bool all_rows = Nr <= 4096;
+    std::vector<int> check_rows;
+    if (all_rows) {
+        check_rows.resize(Nr);
+        std::iota(check_rows.begin(), check_rows.end(), 0);
+    } else {
+        check_rows = sample(rng, Nr, 256, {});
+    }
+    const CMat Zc = E.rows(check_rows);
+    double zc2 = 0.0;
+    for (const cd &z : Zc.a) zc2 += std::norm(z);
+
+    auto rel_error = [&](const CMat &U0, const std::vector<double> &s, const CMat &Vh, int rk) {
+        double e2 = 0.0;
+        std::vector<double> part(check_rows.size(), 0.0);
+        parallel_for((int)check_rows.size(), [&](int i) {
+            int j = check_rows[i];
+            std::vector<cd> coef(rk);
+            for (int l = 0; l < rk; ++l) coef[l] = U0(j, l) * s[l];
+            double acc = 0.0;
+            for (int c = 0; c < Nc; ++c) {
+                cd v(0.0, 0.0);
+                for (int l = 0; l < rk; ++l) v += coef[l] * Vh(l, c);
+                acc += std::norm(Zc(i, c) - v);
+            }
+            part[i] = acc;
+        });
+        for (double p : part) e2 += p;
+        return std::sqrt(e2 / zc2);
+    };
+
+    for (int round = 0;; ++round) {
+        ax.rsvd_rounds = round + 1;
+        const int qr = std::max(1, opt.oversample) * r;
+        std::vector<int> Pcol, Prow;
+        CMat ZJ;
+        std::vector<int> J;
+        for (int it = 0; it < std::max(1, opt.iterations); ++it) {
+            // step 2: sampled rows plus the current important rows; pivoted QR
+            std::vector<int> I = merged(sample(rng, Nr, qr, Prow), Prow);
+            CMat ZI = E.rows(I);
+            std::vector<int> perm = pivoted_qr(ZI, r, nullptr);
+            Pcol.assign(perm.begin(), perm.begin() + std::min<int>(r, (int)perm.size()));
+            std::sort(Pcol.begin(), Pcol.end());
+            // step 3: sampled columns plus the important columns; pivoted LQ
+            J = merged(sample(rng, Nc, qr, Pcol), Pcol);
+            ZJ = E.cols(J);
+            perm = pivoted_qr(adjoint(ZJ), r, nullptr);
+            Prow.assign(perm.begin(), perm.begin() + std::min<int>(r, (int)perm.size()));
+            std::sort(Prow.begin(), Prow.end());
+        }
+        const int rc = (int)Pcol.size(), rr = (int)Prow.size();
+        // step 5: orthonormal bases of the important columns and rows
+        CMat Zpc(Nr, rc);
+        for (int i = 0; i < rc; ++i) {
+            int pos = (int)(std::lower_bound(J.begin(), J.end(), Pcol[i]) - J.begin());
+            for (int j = 0; j < Nr; ++j) Zpc(j, i) = ZJ(j, pos);
+        }
+        CMat Qcol, Qrow;
+        pivoted_qr(Zpc, rc, &Qcol);
+        CMat Zpr = E.rows(Prow);
+        pivoted_qr(adjoint(Zpr), rr, &Qrow);
+        // step 6: middle matrix by least squares on extra sampled rows/columns
+        std::vector<int> J2 = merged(Pcol, sample(rng, Nc, qr, Pcol));
+        std::vector<int> I2 = merged(Prow, sample(rng, Nr, qr, Prow));
+        CMat ZI2 = E.rows(I2);
+        CMat ZIJ((int)I2.size(), (int)J2.size());
+        for (int i = 0; i < (int)I2.size(); ++i)
+            for (int c = 0; c < (int)J2.size(); ++c) ZIJ(i, c) = ZI2(i, J2[c]);
+        CMat A1((int)I2.size(), rc);
+        for (int i = 0; i < (int)I2.size(); ++i)
+            for (int l = 0; l < rc; ++l) A1(i, l) = Qcol(I2[i], l);
+        CMat B1(rr, (int)J2.size());
+        for (int l = 0; l < rr; ++l)
+            for (int c = 0; c < (int)J2.size(); ++c) B1(l, c) = std::conj(Qrow(J2[c], l));
+        CMat M = matmul(matmul(pinv(A1), ZIJ), pinv(B1));
+        // step 7: SVD of the middle matrix
+        CMat UM, VM;
+        std::vector<double> s;
+        svd(M, UM, s, VM);
+        CMat U0 = matmul(Qcol, UM);
+        CMat Vh = matmul(adjoint(VM), adjoint(Qrow));
+        const int rk = (int)s.size();
+        double err_full = rel_error(U0, s, Vh, rk);
+        // truncate: drop the tail whose Frobenius mass is below tol/2
+        double fro2 = 0.0;
+        for (double v : s) fro2 += v * v;
+        int keep = rk;
+        double tail2 = 0.0;
+        while (keep > 0) {
+            double t2 = tail2 + s[keep - 1] * s[keep - 1];
+            if (std::sqrt(t2 / std::max(fro2, 1e-300)) > 0.5 * tol) break;
+            tail2 = t2;
+            --keep;
+        }
+        bool last = (r >= rmax);
+        if (err_full <= 0.5 * tol || last) {
+            double err = rel_error(U0, s, Vh, keep);
+            if (err > tol && keep < rk) {
+                keep = rk;
+                err = err_full;
+            }
+            if (err > tol && !last) {
+                r = std::min(rmax, (int)std::ceil(1.5 * r) + 2);
+                continue;
+            }
+            ax.rank = keep;
+            ax.rel_err = err;
+            ax.fro = std::sqrt(zc2 * (all_rows ? 1.0 : (double)Nr / check_rows.size()));
+            ax.U.assign((size_t)keep * Nr, cd(0.0, 0.0));
+            ax.V.assign((size_t)keep * ax.L, cd(0.0, 0.0));
+            for (int l = 0; l < keep; ++l) {
+                double sh = std::sqrt(s[l]);
+                for (int j = 0; j < Nr; ++j) ax.U[(size_t)l * Nr + j] = U0(j, l) * sh;
+                for (int c = 0; c < Nc; ++c) ax.V[(size_t)l * ax.L + E.nu0 + c] = Vh(l, c) * sh;
+            }
+            if (err > tol)
+                throw std::runtime_error("randomized SVD did not reach the requested tolerance");
+            return;
+        }
+        r = std::min(rmax, (int)std::ceil(1.5 * r) + 2);
+    }
+}
+
+// ------------------------------------------------------------------ build
+void build_axis(AxisPlan &ax, int n, double a, double b, double tol, const PlanOptions &opt)
+{
+    if (n < 1 || n > (1 << 14)) throw std::invalid_argument("n must be in [1, 16384]");
+    if (!(a > -1.0) || !(b > -1.0) || !(a < 1.0) || !(b < 1.0))
+        throw std::invalid_argument("a and b must lie in (-1, 1)");
+    if (!(tol >= 1e-14) || !(tol <= 1e-2)) throw std::invalid_argument("tol must lie in [1e-14, 1e-2]");
+    ax = AxisPlan();
+    ax.n = n; ax.a = a; ax.b = b; ax.tol = tol;
+    int L = 64;
+    while (L < n) L *= 2;
+    ax.L = L;
+    ax.nu0 = (n < opt.dense_below) ? n : std::min(opt.nu0, n);
+    ax.seed = opt.seed ? opt.seed : mix_key(n, a, b, tol);
+
+    Rec rec = recurrence(n + 1, a, b);
+    std::vector<ld> tl;
+    nodes_ld(rec, n, a, b, tl);
+    Evaluator E;
+    E.n = n; E.nu0 = ax.nu0; E.L = L; E.Nc = n - ax.nu0; E.rec = rec;
+    E.x.resize(n); E.sw.resize(n); E.invpw.resize(n); E.q0.resize(n); E.m.resize(n);
+    ax.t.resize(n); ax.x.resize(n); ax.omega.resize(n); ax.bins.resize(n);
+    parallel_for(n, [&](int j) {
+        ld t = tl[j];
+        ld xj = cosl(t);
+        ld om = weight_at(rec, n, xj);
+        ld sh = sinl(t / 2), ch = cosl(t / 2);
+        ld omx = 2 * sh * sh, opx = 2 * ch * ch;  // 1 - x, 1 + x without cancellation
+        ld wx = powl(omx, (ld)a) * powl(opx, (ld)b);
+        E.x[j] = xj;
+        E.sw[j] = sqrtl(om);
+        E.invpw[j] = 1 / (kPi * wx);
+        E.m[j] = (int)llrintl(t * L / (2 * kPi));
+        ax.t[j] = (double)t;
+        ax.x[j] = (double)xj;
+        ax.omega[j] = (double)om;
+        ax.bins[j] = E.m[j];
+        if (E.Nc > 0) E.q0[j] = hilbert_weight_parts(omx, opx, a, b) / rec.sqrt_mu0;
+    });
+    // bins are non-decreasing (nodes ascend in t); CSR over m = 0 .. L/2
+    const int nb = L / 2 + 1;
+    ax.binptr.assign(nb + 1, 0);
+    for (int j = 0; j < n; ++j) {
+        if (ax.bins[j] < 0 || ax.bins[j] > L / 2) throw std::runtime_error("bin out of range");
+        if (j && ax.bins[j] < ax.bins[j - 1]) throw std::runtime_error("bins not monotone");
+        ax.binptr[ax.bins[j] + 1]++;
+    }
+    ax.max_per_bin = 0;
+    for (int m = 0; m < nb; ++m) {
+        ax.max_per_bin = std::max(ax.max_per_bin, ax.binptr[m + 1]);
+        ax.binptr[m + 1] += ax.binptr[m];
+    }
+    // direct block
+    ax.WV.assign((size_t)ax.nu0 * n, 0.0);
+    parallel_for(n, [&](int j) {
+        E.walk(j, ax.nu0 - 1, [&](int k, ld p, ld) { ax.WV[(size_t)k * n + j] = (double)(E.sw[j] * p); });
+    });
+    // DFT phase table of eq. (45): exp(-2 pi i p / L), exact integer phase
+    E.ph.resize(L);
+    for (int p = 0; p < L; ++p) {
+        ld ang = -2 * kPi * p / L;
+        E.ph[p] = cd((double)cosl(ang), (double)sinl(ang));
+    }
+    if (E.Nc > 0)
+        rsvd(E, tol, opt, ax.seed, ax);
+}
+
+void exact_entries(const AxisPlan &ax, int count, const int *rows, const int *degs, cd *out)
+{
+    Rec rec = recurrence(ax.n + 1, ax.a, ax.b);
+    for (int i = 0; i < count; ++i) {
+        int j = rows[i], k = degs[i];
+        if (j < 0 || j >= ax.n || k < 0 || k >= ax.n) throw std::invalid_argument("entry index out of range");
+        ld t = ax.t[j];
+        ld xj = cosl(t);
+        ld sh = sinl(t / 2), ch = cosl(t / 2);
+        ld omx = 2 * sh * sh, opx = 2 * ch * ch;
+        ld wx = powl(omx, (ld)ax.a) * powl(opx, (ld)ax.b);
+        ld q = hilbert_weight_parts(omx, opx, ax.a, ax.b) / rec.sqrt_mu0;
+        ld pm = 0, p = 1 / rec.sqrt_mu0, qm = 0;
+        for (int kk = 0; kk < k; ++kk) {
+            ld ib = 1 / rec.be[kk + 1];
+            ld pn = ((xj - rec.al[kk]) * p - rec.be[kk] * pm) * ib;
+            ld qn = ((xj - rec.al[kk]) * q - rec.be[kk] * qm + (kk == 0 ? rec.sqrt_mu0 : 0)) * ib;
+            pm = p; p = pn;
+            qm = q; q = qn;
+        }
+        ld sw = sqrtl((ld)ax.omega[j]);
+        int64_t e = ((int64_t)ax.bins[j] * k) % ax.L;
+        ld ang = -2 * kPi * e / ax.L;
+        cd z((double)(sw * p), (double)(sw * q / (kPi * wx)));
+        out[i] = z * cd((double)cosl(ang), (double)sinl(ang));
+    }
+}
+
+// ------------------------------------------------------------------ packing
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t layout_axis(AxisPlan &ax, size_t base)
+{
+    size_t o = align256(base);
+    const size_t n = ax.n, L = ax.L, r = ax.rank, nu = ax.nu0;
+    ax.off_tw64 = o;   o = align256(o + L * 16);
+    ax.off_tw32 = o;   o = align256(o + L * 8);
+    ax.off_bins = o;   o = align256(o + n * 4);
+    ax.off_binptr = o; o = align256(o + (L / 2 + 2) * 4);
+    ax.off_wv64 = o;   o = align256(o + nu * n * 8);
+    ax.off_wv32 = o;   o = align256(o + nu * n * 4);
+    ax.off_wvt64 = o;  o = align256(o + nu * n * 8);
+    ax.off_wvt32 = o;  o = align256(o + nu * n * 4);
+    ax.off_u64 = o;    o = align256(o + r * n * 16);
+    ax.off_u32 = o;    o = align256(o + r * n * 8);
+    ax.off_v64 = o;    o = align256(o + r * L * 16);
+    ax.off_v32 = o;    o = align256(o + r * L * 8);
+    ax.bytes = o - base;
+    return o;
+}
+
+void pack_axis(const AxisPlan &ax, unsigned char *blob)
+{
+    const int n = ax.n, L = ax.L, r = ax.rank, nu = ax.nu0;
+    double *tw64 = (double *)(blob + ax.off_tw64);
+    float *tw32 = (float *)(blob + ax.off_tw32);
+    for (int p = 0; p < L; ++p) {
+        // DFT twiddles of eq. (47): exp(+2 pi i p / L)
+        ld ang = 2 * kPi * p / L;
+        ld c = cosl(ang), s = sinl(ang);
+        tw64[2 * p] = (double)c; tw64[2 * p + 1] = (double)s;
+        tw32[2 * p] = (float)c; tw32[2 * p + 1] = (float)s;
+    }
+    std::memcpy(blob + ax.off_bins, ax.bins.data(), (size_t)n * 4);
+    int32_t *bp = (int32_t *)(blob + ax.off_binptr);
+    for (int m = 0; m < L / 2 + 2; ++m) bp[m] = (m < (int)ax.binptr.size()) ? ax.binptr[m] : n;
+    double *wv64 = (double *)(blob + ax.off_wv64);
+    float *wv32 = (float *)(blob + ax.off_wv32);
+    for (size_t i = 0; i < (size_t)nu * n; ++i) { wv64[i] = ax.WV[i]; wv32[i] = (float)ax.WV[i]; }
+    double *wvt64 = (double *)(blob + ax.off_wvt64);
+    float *wvt32 = (float *)(blob + ax.off_wvt32);
+    for (int k = 0; k < nu; ++k)
+        for (int j = 0; j < n; ++j) {
+            double w = ax.WV[(size_t)k * n + j];
+            wvt64[(size_t)j * nu + k] = w;
+            wvt32[(size_t)j * nu + k] = (float)w;
+        }
+    double *u64 = (double *)(blob + ax.off_u64);
+    float *u32 = (float *)(blob + ax.off_u32);
+    for (size_t i = 0; i < (size_t)r * n; ++i) {
+        u64[2 * i] = ax.U[i].real(); u64[2 * i + 1] = ax.U[i].imag();
+        u32[2 * i] = (float)ax.U[i].real(); u32[2 * i + 1] = (float)ax.U[i].imag();
+    }
+    double *v64 = (double *)(blob + ax.off_v64);
+    float *v32 = (float *)(blob + ax.off_v32);
+    for (size_t i = 0; i < (size_t)r * L; ++i) {
+        v64[2 * i] = ax.V[i].real(); v64[2 * i + 1] = ax.V[i].imag();
+        v32[2 * i] = (float)ax.V[i].real(); v32[2 * i + 1] = (float)ax.V[i].imag();
+    }
+}
+
+}  // namespace jt
