@@ -144,6 +144,11 @@ jt_status jt_plan_device_bytes(jt_plan_t plan, size_t *bytes);
  * Errors: JT_EINVAL, JT_ENOMEM (buffer too small), JT_EDEVICE. */
 jt_status jt_plan_bind(jt_plan_t plan, void *dev_buf, size_t bytes, void *stream);
 
+/* Copy the packed factor image (jt_plan_device_bytes bytes) into caller host
+ * memory, for callers that move it to the device themselves or want to check
+ * a bound copy.  Errors: JT_EINVAL, JT_ENOMEM (buffer too small). */
+jt_status jt_plan_pack(jt_plan_t plan, void *host_dst, size_t bytes);
+
 /* Device workspace a transform needs beyond its input and output: always 0
  * (every axis pass works in place on the output buffer). */
 jt_status jt_workspace_bytes(jt_plan_t plan, jt_prec prec, size_t *bytes);

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libjt.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
-        "libjt.so not found at %s; build it with `python -m paper_1901_07275_amd.build`" % LIB_PATH)
+        "libjt.so not found at %s; build it with `python paper_1901_07275_amd/build.py`" % LIB_PATH)
 
 _lib = ctypes.CDLL(LIB_PATH)
 
@@ -60,6 +60,7 @@ SYMBOLS = {
     "jt_plan_entries": [_vp, ctypes.c_int, ctypes.c_int, _ip, _ip, _dp],
     "jt_plan_device_bytes": [_vp, ctypes.POINTER(ctypes.c_size_t)],
     "jt_plan_bind": [_vp, _vp, ctypes.c_size_t, _vp],
+    "jt_plan_pack": [_vp, _vp, ctypes.c_size_t],
     "jt_workspace_bytes": [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)],
     "jt_forward": [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp],
     "jt_inverse": [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp],
@@ -121,7 +122,7 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and _lib is not None:
             _lib.jt_plan_destroy(h)
             self._h = None
 
@@ -166,6 +167,12 @@ class Plan:
         b = ctypes.c_size_t()
         _check(_lib.jt_plan_device_bytes(self._h, ctypes.byref(b)))
         return b.value
+
+    def pack(self) -> np.ndarray:
+        """Host copy of the packed factor image that bind() places on the device."""
+        out = np.empty(self.device_bytes(), dtype=np.uint8)
+        _check(_lib.jt_plan_pack(self._h, _vp(out.ctypes.data), out.nbytes))
+        return out
 
     # ------------------------------------------------------------ device side
     def bind(self, device=None, stream=None):

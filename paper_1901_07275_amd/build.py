@@ -1,6 +1,6 @@
 """Compile the HIP/C++ library libjt.so for gfx950 (in-tree).
 
-Usage:  python -m paper_1901_07275_amd.build      (or build() from Python)
+Usage:  python paper_1901_07275_amd/build.py   (run by path: importing the package needs libjt.so)
 """
 from __future__ import annotations
 

@@ -106,6 +106,7 @@ jt_status run_axis(jt_plan_t p, int axis, bool forward, const void *in, jt_dtype
     a.u = d + (f32 ? ax.off_u32 : ax.off_u64);
     a.v = d + (f32 ? ax.off_v32 : ax.off_v64);
     if (!f32 && ax.L > 8192) return fail(JT_EUNSUPPORTED, "fp64 path supports n <= 8192");
+    if (total_elems(p) >= (1LL << 31)) return fail(JT_EUNSUPPORTED, "tensors must hold fewer than 2^31 elements");
     hipError_t e = jt::launch_axis(a, reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess) return fail(JT_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
     return JT_OK;
@@ -278,6 +279,14 @@ jt_status jt_plan_bind(jt_plan_t plan, void *dev_buf, size_t bytes, void *stream
     e = hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess) return fail(JT_EDEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
     plan->dev = static_cast<unsigned char *>(dev_buf);
+    return ok();
+}
+
+jt_status jt_plan_pack(jt_plan_t plan, void *host_dst, size_t bytes)
+{
+    if (!plan || !host_dst) return fail(JT_EINVAL, "null argument");
+    if (bytes < plan->dev_bytes) return fail(JT_ENOMEM, "host buffer smaller than jt_plan_device_bytes");
+    std::memcpy(host_dst, plan->blob.data(), plan->dev_bytes);
     return ok();
 }
 

@@ -178,13 +178,14 @@ struct Geo {
     static constexpr int BUF = L + L / 16;           // padded line buffer (complex)
 };
 
-// Lane-constant twiddles of all passes after the first.  Small blocks keep
-// them in registers for the whole kernel; blocks of 512+ threads (L >= 8192)
-// have too few registers per lane and read them from the table when used.
+// Twiddles of all passes after the first.  They depend only on the lane, so
+// the fp32 kernels keep them in registers for the whole kernel; the fp64
+// kernels (twice the register cost) and blocks of 512+ threads read them from
+// the L-entry table when a pass needs them.
 template <class T, int LOG2L>
 struct Twiddles {
     using G = Geo<LOG2L>;
-    static constexpr bool kHoist = G::BLOCK <= 256;
+    static constexpr bool kHoist = (sizeof(T) == 4) && (G::BLOCK <= 256);
     cpx<T> mid_[(kHoist && G::NMID > 0) ? G::NMID : 1][15];
     cpx<T> fin_[(kHoist && G::RF > 1) ? 16 / G::RF : 1][(G::RF > 1) ? G::RF - 1 : 1];
     const cpx<T> *tw;
@@ -195,7 +196,7 @@ struct Twiddles {
     {
         int ns = 16;
         for (int k = 0; k < i; ++k) ns *= 16;
-        return (p % ns) * r * (G::L / (16 * ns));
+        return (p & (ns - 1)) * r * (G::L / (16 * ns));
     }
     // final pass (radix RF, Ns = L/RF): task j = p + P t, factor omega_L^{j r}
     static __device__ __forceinline__ int fin_index(int t, int r, int p) { return (p + G::P * t) * r; }
@@ -236,11 +237,9 @@ template <class T, int LOG2L>
 __device__ __forceinline__ void fft_line(cpx<T> *v, cpx<T> *buf, int p, const Twiddles<T, LOG2L> &tw)
 {
     using G = Geo<LOG2L>;
+    static_assert(G::L >= 64, "lines shorter than 64 use the dense path with L = 64");
     // pass 0: Ns = 1, no twiddles, inputs are already v[r] = x[p + r P]
     dft16(v);
-    if constexpr (G::S16 == 1 && G::RF == 1) {
-        return;  // L = 16 (not instantiated)
-    }
 #pragma unroll
     for (int r = 0; r < 16; ++r) buf[pad(p * 16 + r)] = v[r];
     int ns = 16;
@@ -255,7 +254,7 @@ __device__ __forceinline__ void fft_line(cpx<T> *v, cpx<T> *buf, int p, const Tw
         const bool last = (G::RF == 1) && (i == G::NMID - 1);
         if (!last) {
             __syncthreads();
-            const int base = (p / ns) * ns * 16 + (p % ns);
+            const int base = (p / ns) * ns * 16 + (p & (ns - 1));
 #pragma unroll
             for (int r = 0; r < 16; ++r) buf[pad(base + r * ns)] = v[r];
         }
@@ -264,44 +263,30 @@ __device__ __forceinline__ void fft_line(cpx<T> *v, cpx<T> *buf, int p, const Tw
     if constexpr (G::RF > 1) {
         constexpr int RF = G::RF, NT = 16 / RF;
         __syncthreads();
-        cpx<T> w[16];
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
+            cpx<T> w[RF];
             const int j = p + G::P * t;
 #pragma unroll
-            for (int r = 0; r < RF; ++r) w[t * RF + r] = buf[pad(j + r * (G::L / RF))];
-        }
+            for (int r = 0; r < RF; ++r) w[r] = buf[pad(j + r * (G::L / RF))];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-#pragma unroll
-            for (int r = 1; r < RF; ++r) w[t * RF + r] = cmul(w[t * RF + r], tw.fin(t, r));
-            dftR<T, RF>(&w[t * RF]);
+            for (int r = 1; r < RF; ++r) w[r] = cmul(w[r], tw.fin(t, r));
+            dftR<T, RF>(w);
             // output index j + r * (L/RF) = p + P (t + r * NT)
 #pragma unroll
-            for (int r = 0; r < RF; ++r) v[t + r * NT] = w[t * RF + r];
+            for (int r = 0; r < RF; ++r) v[t + r * NT] = w[r];
         }
     }
 }
 
-template <class T>
-__device__ __forceinline__ T load_elem(const void *p, long long i, int f64)
-{
-    return f64 ? (T)((const double *)p)[i] : (T)((const float *)p)[i];
-}
-__device__ __forceinline__ void store_elem(void *p, long long i, int f64, double v)
-{
-    if (f64) ((double *)p)[i] = v;
-    else ((float *)p)[i] = (float)v;
-}
-
 // Blocks that share an XCD get neighbouring lines, so that the strided passes
 // reuse cache lines within one L2.
-__device__ __forceinline__ long long block_line(long long lpb)
+__device__ __forceinline__ unsigned block_line(unsigned lpb)
 {
     const unsigned b = blockIdx.x, g = gridDim.x;
     unsigned lb = b;
     if ((g & 7u) == 0u) lb = (b & 7u) * (g >> 3) + (b >> 3);
-    return (long long)lb * lpb;
+    return lb * lpb;
 }
 
 template <class T, int LOG2L, int FWD>
@@ -314,11 +299,13 @@ __global__ void __launch_bounds__(Geo<LOG2L>::BLOCK) axis_pass(AxisLaunch a)
     cpx<T> *buf = smem + slot * G::BUF;
     T *sbuf = reinterpret_cast<T *>(buf);
 
-    const long long line = block_line(G::LPB) + slot;
-    const bool active = line < a.lines;
-    const long long outer = active ? line / a.stride : 0;
-    const long long inner = active ? line % a.stride : 0;
-    const long long base = outer * (long long)a.n * a.stride + inner;
+    // the host guarantees lines * n < 2^31, so 32-bit indexing is exact
+    const unsigned line = block_line(G::LPB) + (unsigned)slot;
+    const bool active = line < (unsigned)a.lines;
+    const unsigned stride = (unsigned)a.stride;
+    const unsigned outer = active ? line / stride : 0u;
+    const unsigned inner = active ? line - outer * stride : 0u;
+    const unsigned base = outer * (unsigned)a.n * stride + inner;
     const int n = a.n, nu0 = a.nu0;
 
     const cpx<T> *tw = reinterpret_cast<const cpx<T> *>(a.tw);
@@ -330,11 +317,22 @@ __global__ void __launch_bounds__(Geo<LOG2L>::BLOCK) axis_pass(AxisLaunch a)
     Twiddles<T, LOG2L> twd;
     twd.load(tw, p);
 
+    // the line, in the lane-owned layout (zero beyond n); dtype branch is uniform
     T x[16];
+    if (a.in_f64) {
+        const double *src = reinterpret_cast<const double *>(a.in);
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int k = p + G::P * q;
-        x[q] = (active && k < n) ? load_elem<T>(a.in, base + (long long)k * a.stride, a.in_f64) : (T)0;
+        for (int q = 0; q < 16; ++q) {
+            const int k = p + G::P * q;
+            x[q] = (active && k < n) ? (T)src[base + (unsigned)k * stride] : (T)0;
+        }
+    } else {
+        const float *src = reinterpret_cast<const float *>(a.in);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int k = p + G::P * q;
+            x[q] = (active && k < n) ? (T)src[base + (unsigned)k * stride] : (T)0;
+        }
     }
     double acc[16];
 
@@ -351,20 +349,14 @@ __global__ void __launch_bounds__(Geo<LOG2L>::BLOCK) axis_pass(AxisLaunch a)
             const int j = p + G::P * q;
             T s = 0;
             if (j < n)
-                for (int k = 0; k < nu0; ++k) s += wv[(long long)k * n + j] * sbuf[k];
+                for (int k = 0; k < nu0; ++k) s += wv[k * n + j] * sbuf[k];
             acc[q] = (double)s;
-        }
-        int mb[16];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int j = p + G::P * q;
-            mb[q] = (j < n) ? a.bins[j] : 0;
         }
         for (int l = 0; l < a.rank; ++l) {
             cpx<T> v[16];
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
-                const cpx<T> f = vf[(long long)l * G::L + p + G::P * q];
+                const cpx<T> f = vf[l * G::L + p + G::P * q];
                 v[q] = {f.x * x[q], f.y * x[q]};
             }
             __syncthreads();  // previous users of buf are done
@@ -380,8 +372,8 @@ __global__ void __launch_bounds__(Geo<LOG2L>::BLOCK) axis_pass(AxisLaunch a)
             for (int q = 0; q < 16; ++q) {
                 const int j = p + G::P * q;
                 if (j < n) {
-                    const cpx<T> y = buf[pad(mb[q])];
-                    const cpx<T> u = uf[(long long)l * n + j];
+                    const cpx<T> y = buf[pad(a.bins[j])];
+                    const cpx<T> u = uf[l * n + j];
                     acc[q] += (double)(u.x * y.x - u.y * y.y);
                 }
             }
@@ -399,15 +391,8 @@ __global__ void __launch_bounds__(Geo<LOG2L>::BLOCK) axis_pass(AxisLaunch a)
             const int k = p + G::P * q;
             T s = 0;
             if (k < nu0)
-                for (int j = 0; j < n; ++j) s += wvt[(long long)j * nu0 + k] * sbuf[j];
+                for (int j = 0; j < n; ++j) s += wvt[j * nu0 + k] * sbuf[j];
             acc[q] = (double)s;
-        }
-        int b0[16], b1[16];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int m = p + G::P * q;
-            b0[q] = (m <= G::L / 2) ? a.binptr[m] : 0;
-            b1[q] = (m <= G::L / 2) ? a.binptr[m + 1] : 0;
         }
         for (int l = 0; l < a.rank; ++l) {
             __syncthreads();  // previous users of buf are done
@@ -415,7 +400,7 @@ __global__ void __launch_bounds__(Geo<LOG2L>::BLOCK) axis_pass(AxisLaunch a)
             for (int q = 0; q < 16; ++q) {
                 const int j = p + G::P * q;
                 if (j < n) {
-                    const cpx<T> u = uf[(long long)l * n + j];
+                    const cpx<T> u = uf[l * n + j];
                     buf[pad(j)] = {u.x * x[q], u.y * x[q]};
                 }
             }
@@ -423,8 +408,12 @@ __global__ void __launch_bounds__(Geo<LOG2L>::BLOCK) axis_pass(AxisLaunch a)
             cpx<T> v[16];
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
+                const int m = p + G::P * q;
                 cpx<T> z = {(T)0, (T)0};
-                for (int jj = b0[q]; jj < b1[q]; ++jj) z = z + buf[pad(jj)];
+                if (m <= G::L / 2) {
+                    const int j0 = a.binptr[m], j1 = a.binptr[m + 1];
+                    for (int jj = j0; jj < j1; ++jj) z = z + buf[pad(jj)];
+                }
                 v[q] = z;
             }
             __syncthreads();
@@ -432,17 +421,27 @@ __global__ void __launch_bounds__(Geo<LOG2L>::BLOCK) axis_pass(AxisLaunch a)
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
                 const int k = p + G::P * q;
-                const cpx<T> f = vf[(long long)l * G::L + k];
+                const cpx<T> f = vf[l * G::L + k];
                 acc[q] += (double)(f.x * v[q].x - f.y * v[q].y);
             }
         }
     }
     // all reads of the input happened before the first barrier, so the
     // output may alias the input (in-place passes)
+    if (a.out_f64) {
+        double *dst = reinterpret_cast<double *>(a.out);
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int i = p + G::P * q;
-        if (active && i < n) store_elem(a.out, base + (long long)i * a.stride, a.out_f64, acc[q]);
+        for (int q = 0; q < 16; ++q) {
+            const int i = p + G::P * q;
+            if (active && i < n) dst[base + (unsigned)i * stride] = acc[q];
+        }
+    } else {
+        float *dst = reinterpret_cast<float *>(a.out);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int i = p + G::P * q;
+            if (active && i < n) dst[base + (unsigned)i * stride] = (float)acc[q];
+        }
     }
 }
 

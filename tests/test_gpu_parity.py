@@ -63,6 +63,23 @@ def bound(prec, tol, d):
     return 20 * tol * d + floor
 
 
+# ------------------------------------------------------------------ smallest cases first
+# Ordered from the simplest kernel path upward (dense block only, then the
+# shortest FFT, then fp64), so that with -x a failure stops at the simplest
+# configuration that shows it.
+@pytest.mark.parametrize("n,prec", [(33, 1), (33, 0), (64, 1), (64, 0), (200, 1), (200, 0)])
+def test_stage_small_1d(jt, orc, n, prec):
+    ab = ((0.15, -0.3),)
+    tol = 1e-12 if prec == 0 else 1e-7
+    plan = plan_for(jt, (n,), ab, tol)
+    al = np.random.default_rng(n).standard_normal(n)
+    g = run(jt, plan, al, "fwd", prec)
+    g_ref = orc.forward(al, ab)
+    assert relerr(g, g_ref) <= bound(prec, tol, 1)
+    a2 = run(jt, plan, g_ref, "inv", prec)
+    assert relerr(a2, al) <= bound(prec, tol, 1)
+
+
 # ------------------------------------------------------------------ benchmark configurations
 def test_c1_forward_inverse_fp64(jt, orc):
     cfg = workloads.C1
