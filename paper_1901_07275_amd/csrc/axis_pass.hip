@@ -162,6 +162,24 @@ __device__ __forceinline__ void dftR(cpx<T> *v)
     else dft16(v);
 }
 
+// Synchronisation of the lanes that share one line buffer.  A line of up to
+// 1024 points lives in one wave: its lanes exchange data through LDS in
+// program order, so a wave-scope fence (no instruction, it only stops the
+// compiler from moving LDS accesses across it) is enough, and the other waves
+// of the block keep running.  Longer lines span several waves and need the
+// block barrier.
+template <int P>
+__device__ __forceinline__ void sync_line()
+{
+    if constexpr (P <= 64) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 // padded LDS index: one spare slot every 16 elements
 __device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
 
@@ -182,10 +200,25 @@ struct Geo {
 // the fp32 kernels keep them in registers for the whole kernel; the fp64
 // kernels (twice the register cost) and blocks of 512+ threads read them from
 // the L-entry table when a pass needs them.
+// Where the per-pass twiddles live: 0 = registers (loaded once), 1 = a copy
+// of the table in LDS (loaded once per block), 2 = the table in global memory.
+#ifndef JT_TW_MODE_F32
+#define JT_TW_MODE_F32 0
+#endif
+#ifndef JT_TW_MODE_F64
+#define JT_TW_MODE_F64 2
+#endif
+template <class T, int LOG2L>
+constexpr int tw_mode()
+{
+    if constexpr (Geo<LOG2L>::BLOCK > 256) return 2;  // big lines: too few registers per lane
+    else return sizeof(T) == 4 ? JT_TW_MODE_F32 : JT_TW_MODE_F64;
+}
+
 template <class T, int LOG2L>
 struct Twiddles {
     using G = Geo<LOG2L>;
-    static constexpr bool kHoist = (sizeof(T) == 4) && (G::BLOCK <= 256);
+    static constexpr bool kHoist = tw_mode<T, LOG2L>() == 0;
     cpx<T> mid_[(kHoist && G::NMID > 0) ? G::NMID : 1][15];
     cpx<T> fin_[(kHoist && G::RF > 1) ? 16 / G::RF : 1][(G::RF > 1) ? G::RF - 1 : 1];
     const cpx<T> *tw;
@@ -245,7 +278,7 @@ __device__ __forceinline__ void fft_line(cpx<T> *v, cpx<T> *buf, int p, const Tw
     int ns = 16;
 #pragma unroll
     for (int i = 0; i < G::NMID; ++i) {
-        __syncthreads();
+        sync_line<G::P>();
 #pragma unroll
         for (int r = 0; r < 16; ++r) v[r] = buf[pad(p + r * G::P)];
 #pragma unroll
@@ -253,7 +286,7 @@ __device__ __forceinline__ void fft_line(cpx<T> *v, cpx<T> *buf, int p, const Tw
         dft16(v);
         const bool last = (G::RF == 1) && (i == G::NMID - 1);
         if (!last) {
-            __syncthreads();
+            sync_line<G::P>();
             const int base = (p / ns) * ns * 16 + (p & (ns - 1));
 #pragma unroll
             for (int r = 0; r < 16; ++r) buf[pad(base + r * ns)] = v[r];
@@ -262,7 +295,7 @@ __device__ __forceinline__ void fft_line(cpx<T> *v, cpx<T> *buf, int p, const Tw
     }
     if constexpr (G::RF > 1) {
         constexpr int RF = G::RF, NT = 16 / RF;
-        __syncthreads();
+        sync_line<G::P>();
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             cpx<T> w[RF];
@@ -289,14 +322,25 @@ __device__ __forceinline__ unsigned block_line(unsigned lpb)
     return lb * lpb;
 }
 
+// Rank split: a block holds S waves that share the same lines; wave s takes
+// the terms l = s, s + S, ... and the S partial sums are added in LDS at the
+// end (fixed order, so results do not depend on timing).  Every wave runs the
+// same number of iterations (ceil(rank / S)) so that all of them meet every
+// block barrier; a wave whose term index runs past the rank computes a term
+// it then discards.
 template <class T, int LOG2L, int FWD>
-__global__ void __launch_bounds__(Geo<LOG2L>::BLOCK) axis_pass(AxisLaunch a)
+__global__ void __launch_bounds__(Geo<LOG2L>::BLOCK == 64 ? 256 : Geo<LOG2L>::BLOCK) axis_pass(AxisLaunch a)
 {
     using G = Geo<LOG2L>;
-    __shared__ cpx<T> smem[G::LPB * G::BUF];
-    const int slot = threadIdx.x / G::P;
-    const int p = threadIdx.x % G::P;
-    cpx<T> *buf = smem + slot * G::BUF;
+    extern __shared__ unsigned char lds_raw[];
+    cpx<T> *smem = reinterpret_cast<cpx<T> *>(lds_raw);
+    // lanes of one split group: G::BLOCK threads (one wave for L <= 1024)
+    const int S = (int)(blockDim.x / G::BLOCK);
+    const int sgrp = (int)threadIdx.x / G::BLOCK;
+    const int tid = (int)threadIdx.x % G::BLOCK;
+    const int slot = tid / G::P;
+    const int p = tid % G::P;
+    cpx<T> *buf = smem + (sgrp * G::LPB + slot) * G::BUF;
     T *sbuf = reinterpret_cast<T *>(buf);
 
     // the host guarantees lines * n < 2^31, so 32-bit indexing is exact
@@ -306,7 +350,7 @@ __global__ void __launch_bounds__(Geo<LOG2L>::BLOCK) axis_pass(AxisLaunch a)
     const unsigned outer = active ? line / stride : 0u;
     const unsigned inner = active ? line - outer * stride : 0u;
     const unsigned base = outer * (unsigned)a.n * stride + inner;
-    const int n = a.n, nu0 = a.nu0;
+    const int n = a.n, nu0 = a.nu0, rank = a.rank;
 
     const cpx<T> *tw = reinterpret_cast<const cpx<T> *>(a.tw);
     const cpx<T> *uf = reinterpret_cast<const cpx<T> *>(a.u);
@@ -315,7 +359,14 @@ __global__ void __launch_bounds__(Geo<LOG2L>::BLOCK) axis_pass(AxisLaunch a)
     const T *wvt = reinterpret_cast<const T *>(a.wvt);
 
     Twiddles<T, LOG2L> twd;
-    twd.load(tw, p);
+    if constexpr (tw_mode<T, LOG2L>() == 1) {
+        cpx<T> *tws = smem + S * G::LPB * G::BUF;
+        for (int i = (int)threadIdx.x; i < G::L; i += (int)blockDim.x) tws[i] = tw[i];
+        __syncthreads();
+        twd.load(tws, p);
+    } else {
+        twd.load(tw, p);
+    }
 
     // the line, in the lane-owned layout (zero beyond n); dtype branch is uniform
     T x[16];
@@ -335,67 +386,76 @@ __global__ void __launch_bounds__(Geo<LOG2L>::BLOCK) axis_pass(AxisLaunch a)
         }
     }
     double acc[16];
+    const int iters = (rank + S - 1) / S;
 
     if constexpr (FWD) {
-        // ---- direct block: out_j = sum_{k<nu0} WV[k][j] alpha_k (alpha_k broadcast via LDS)
+        // ---- direct block (split group 0): out_j = sum_{k<nu0} WV[k][j] alpha_k
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int k = p + G::P * q;
             if (k < nu0) sbuf[k] = x[q];
         }
-        __syncthreads();
+        sync_line<G::P>();
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int j = p + G::P * q;
             T s = 0;
-            if (j < n)
+            if (sgrp == 0 && j < n)
                 for (int k = 0; k < nu0; ++k) s += wv[k * n + j] * sbuf[k];
             acc[q] = (double)s;
         }
-        for (int l = 0; l < a.rank; ++l) {
+        for (int it = 0; it < iters; ++it) {
+            const int l0 = it * S + sgrp;
+            const bool keep = l0 < rank;
+            const int l = keep ? l0 : rank - 1;
             cpx<T> v[16];
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
                 const cpx<T> f = vf[l * G::L + p + G::P * q];
                 v[q] = {f.x * x[q], f.y * x[q]};
             }
-            __syncthreads();  // previous users of buf are done
+            sync_line<G::P>();  // previous users of buf are done
             fft_line<T, LOG2L>(v, buf, p, twd);
-            __syncthreads();
+            sync_line<G::P>();
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
                 const int m = p + G::P * q;
                 if (m <= G::L / 2) buf[pad(m)] = v[q];
             }
-            __syncthreads();
+            sync_line<G::P>();
+            if (keep) {
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int j = p + G::P * q;
-                if (j < n) {
-                    const cpx<T> y = buf[pad(a.bins[j])];
-                    const cpx<T> u = uf[l * n + j];
-                    acc[q] += (double)(u.x * y.x - u.y * y.y);
+                for (int q = 0; q < 16; ++q) {
+                    const int j = p + G::P * q;
+                    if (j < n) {
+                        const cpx<T> y = buf[pad(a.bins[j])];
+                        const cpx<T> u = uf[l * n + j];
+                        acc[q] += (double)(u.x * y.x - u.y * y.y);
+                    }
                 }
             }
         }
     } else {
-        // ---- direct block: alpha_k = sum_j WV[k][j] g_j for k < nu0 (g broadcast via LDS)
+        // ---- direct block (split group 0): alpha_k = sum_j WV[k][j] g_j for k < nu0
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int j = p + G::P * q;
             if (j < n) sbuf[j] = x[q];
         }
-        __syncthreads();
+        sync_line<G::P>();
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int k = p + G::P * q;
             T s = 0;
-            if (k < nu0)
+            if (sgrp == 0 && k < nu0)
                 for (int j = 0; j < n; ++j) s += wvt[j * nu0 + k] * sbuf[j];
             acc[q] = (double)s;
         }
-        for (int l = 0; l < a.rank; ++l) {
-            __syncthreads();  // previous users of buf are done
+        for (int it = 0; it < iters; ++it) {
+            const int l0 = it * S + sgrp;
+            const bool keep = l0 < rank;
+            const int l = keep ? l0 : rank - 1;
+            sync_line<G::P>();  // previous users of buf are done
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
                 const int j = p + G::P * q;
@@ -404,7 +464,7 @@ __global__ void __launch_bounds__(Geo<LOG2L>::BLOCK) axis_pass(AxisLaunch a)
                     buf[pad(j)] = {u.x * x[q], u.y * x[q]};
                 }
             }
-            __syncthreads();
+            sync_line<G::P>();
             cpx<T> v[16];
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
@@ -416,31 +476,48 @@ __global__ void __launch_bounds__(Geo<LOG2L>::BLOCK) axis_pass(AxisLaunch a)
                 }
                 v[q] = z;
             }
-            __syncthreads();
+            sync_line<G::P>();
             fft_line<T, LOG2L>(v, buf, p, twd);
+            if (keep) {
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int k = p + G::P * q;
-                const cpx<T> f = vf[l * G::L + k];
-                acc[q] += (double)(f.x * v[q].x - f.y * v[q].y);
+                for (int q = 0; q < 16; ++q) {
+                    const int k = p + G::P * q;
+                    const cpx<T> f = vf[l * G::L + k];
+                    acc[q] += (double)(f.x * v[q].x - f.y * v[q].y);
+                }
             }
         }
     }
-    // all reads of the input happened before the first barrier, so the
-    // output may alias the input (in-place passes)
+    // ---- sum the S partial results in LDS (fixed order), then store.
+    // All reads of the input happened before the first barrier, so the output
+    // may alias the input (in-place passes).
+    double *part = reinterpret_cast<double *>(buf);  // L doubles fit in one line buffer
+    if (S > 1) {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 16; ++q) part[p + G::P * q] = acc[q];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            double t = 0.0;
+            for (int s2 = 0; s2 < S; ++s2)
+                t += reinterpret_cast<const double *>(smem + (s2 * G::LPB + slot) * G::BUF)[p + G::P * q];
+            acc[q] = t;
+        }
+    }
     if (a.out_f64) {
         double *dst = reinterpret_cast<double *>(a.out);
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int i = p + G::P * q;
-            if (active && i < n) dst[base + (unsigned)i * stride] = acc[q];
+            if (active && i < n && (q % S) == sgrp) dst[base + (unsigned)i * stride] = acc[q];
         }
     } else {
         float *dst = reinterpret_cast<float *>(a.out);
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int i = p + G::P * q;
-            if (active && i < n) dst[base + (unsigned)i * stride] = (float)acc[q];
+            if (active && i < n && (q % S) == sgrp) dst[base + (unsigned)i * stride] = (float)acc[q];
         }
     }
 }
@@ -452,10 +529,28 @@ hipError_t launch_t(const AxisLaunch &a, hipStream_t s)
     const long long blocks = (a.lines + G::LPB - 1) / G::LPB;
     if (blocks <= 0) return hipSuccess;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    // rank split: aim for about 4 waves per SIMD (256 CUs x 4 SIMDs), only
+    // for lines held by a single wave, at most 4 ways and never beyond the rank
+    int S = 1;
+    if (G::BLOCK == 64) {
+        const long long target = 4LL * 4 * 256;
+        while (S < 4 && S < a.rank && blocks * S < target) S *= 2;
+    }
+    const size_t lds = ((size_t)S * G::LPB * G::BUF + (tw_mode<T, LOG2L>() == 1 ? G::L : 0)) * sizeof(cpx<T>);
+    const dim3 grid((unsigned)blocks), block((unsigned)(G::BLOCK * S));
+    // allow dynamic LDS beyond 64 KB (gfx950 has 160 KB per CU); once per kernel
+    static bool attr_set[2] = {false, false};
+    if (!attr_set[a.forward ? 1 : 0]) {
+        const void *fn = a.forward ? reinterpret_cast<const void *>(&axis_pass<T, LOG2L, 1>)
+                                   : reinterpret_cast<const void *>(&axis_pass<T, LOG2L, 0>);
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        (void)hipGetLastError();
+        attr_set[a.forward ? 1 : 0] = true;
+    }
     if (a.forward)
-        hipLaunchKernelGGL((axis_pass<T, LOG2L, 1>), dim3((unsigned)blocks), dim3(G::BLOCK), 0, s, a);
+        hipLaunchKernelGGL((axis_pass<T, LOG2L, 1>), grid, block, lds, s, a);
     else
-        hipLaunchKernelGGL((axis_pass<T, LOG2L, 0>), dim3((unsigned)blocks), dim3(G::BLOCK), 0, s, a);
+        hipLaunchKernelGGL((axis_pass<T, LOG2L, 0>), grid, block, lds, s, a);
     return hipGetLastError();
 }
 
