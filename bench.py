@@ -40,6 +40,25 @@ def axis_flops(n: int, L: int, nu0: int, rank: int, lines: int) -> float:
     return per_line * lines
 
 
+def measured_traffic(kernel_prefix: str):
+    """HBM bytes per launch of the given kernel family from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when the kernel source
+    changed after the counters were taken."""
+    import hashlib
+
+    prof = os.path.join(ROOT, "profiles", "axis_pass_2d_n1024_traffic.json")
+    src = os.path.join(ROOT, "paper_1901_07275_amd", "csrc", "axis_pass.hip")
+    try:
+        rec = json.load(open(prof))
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256_16") != h:
+        return None
+    vals = [v["hbm_bytes"] for k, v in rec["kernels"].items() if kernel_prefix in k]
+    return float(np.mean(vals)) if vals else None
+
+
 def percentile(xs, q):
     return float(np.percentile(np.asarray(xs), q))
 
@@ -88,6 +107,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (5 times), to calibrate "
+                         "rocprofv3 FETCH_SIZE/WRITE_SIZE against known bytes")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -95,6 +117,16 @@ def main() -> int:
         return 2
 
     import torch
+
+    if args.copy_probe:
+        nbytes = args.copy_probe << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": nbytes, "launches": 5}))
+        return 0
 
     import paper_1901_07275_amd as jt
 
@@ -138,12 +170,13 @@ def main() -> int:
     avg_launch_flops = float(np.mean(head["launch_flops"]))
     achieved = avg_launch_flops / (avg_launch_ms * 1e-3) / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / (PEAK_FP32 / 1e12), "traffic": None,
+            "frac": achieved / (PEAK_FP32 / 1e12), "traffic": measured_traffic("axis_pass<float, 10"),
             "kernel": "axis_pass<float,10>", "launch_ms": avg_launch_ms, "flops_per_launch": avg_launch_flops}
     r64 = results["fp64"]
     ach64 = float(np.mean(r64["launch_flops"])) / (float(np.mean(r64["launch_ms"])) * 1e-3) / 1e12
     r64["roofline"] = {"bound": "alu", "achieved": ach64, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
-                       "frac": ach64 / (PEAK_FP64 / 1e12), "kernel": "axis_pass<double,10>"}
+                       "frac": ach64 / (PEAK_FP64 / 1e12), "kernel": "axis_pass<double,10>",
+                       "traffic": measured_traffic("axis_pass<double, 10")}
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -94,6 +94,7 @@ jt_status run_axis(jt_plan_t p, int axis, bool forward, const void *in, jt_dtype
     a.L = ax.L;
     a.nu0 = ax.nu0;
     a.rank = ax.rank;
+    a.max_per_bin = ax.max_per_bin;
     a.forward = forward ? 1 : 0;
     a.fp32 = (prec == JT_PREC_FP32_BULK);
     const bool f32 = a.fp32;

@@ -201,9 +201,11 @@ struct Geo {
 // kernels (twice the register cost) and blocks of 512+ threads read them from
 // the L-entry table when a pass needs them.
 // Where the per-pass twiddles live: 0 = registers (loaded once), 1 = a copy
-// of the table in LDS (loaded once per block), 2 = the table in global memory.
+// of the table in LDS (loaded once per block), 2 = the table in global memory
+// (L1/L2 resident).  Measured on the 1024-point lines, 2 is fastest in both
+// precisions: registers are better spent on occupancy.
 #ifndef JT_TW_MODE_F32
-#define JT_TW_MODE_F32 0
+#define JT_TW_MODE_F32 2
 #endif
 #ifndef JT_TW_MODE_F64
 #define JT_TW_MODE_F64 2
@@ -387,6 +389,10 @@ __global__ void __launch_bounds__(Geo<LOG2L>::BLOCK == 64 ? 256 : Geo<LOG2L>::BL
     }
     double acc[16];
     const int iters = (rank + S - 1) / S;
+#ifndef JT_FULL_FAST
+#define JT_FULL_FAST 1
+#endif
+    const bool full = JT_FULL_FAST && (n == G::L);  // uniform: the line fills every owned slot
 
     if constexpr (FWD) {
         // ---- direct block (split group 0): out_j = sum_{k<nu0} WV[k][j] alpha_k
@@ -396,13 +402,28 @@ __global__ void __launch_bounds__(Geo<LOG2L>::BLOCK == 64 ? 256 : Geo<LOG2L>::BL
             if (k < nu0) sbuf[k] = x[q];
         }
         sync_line<G::P>();
+        if (full) {
+            // all 16 outputs exist: one batch of 16 loads per degree k
+            T s[16];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int j = p + G::P * q;
-            T s = 0;
-            if (sgrp == 0 && j < n)
-                for (int k = 0; k < nu0; ++k) s += wv[k * n + j] * sbuf[k];
-            acc[q] = (double)s;
+            for (int q = 0; q < 16; ++q) s[q] = 0;
+            const int kmax = (sgrp == 0) ? nu0 : 0;
+            for (int k = 0; k < kmax; ++k) {
+                const T ak = sbuf[k];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) s[q] += wv[k * n + p + G::P * q] * ak;
+            }
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[q] = (double)s[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int j = p + G::P * q;
+                T s = 0;
+                if (sgrp == 0 && j < n)
+                    for (int k = 0; k < nu0; ++k) s += wv[k * n + j] * sbuf[k];
+                acc[q] = (double)s;
+            }
         }
         for (int it = 0; it < iters; ++it) {
             const int l0 = it * S + sgrp;
@@ -424,13 +445,25 @@ __global__ void __launch_bounds__(Geo<LOG2L>::BLOCK == 64 ? 256 : Geo<LOG2L>::BL
             }
             sync_line<G::P>();
             if (keep) {
+                const cpx<T> *ul = uf + l * n;
+                if (full) {
+                    // every owned node exists: no per-element guards, loads batch
 #pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    const int j = p + G::P * q;
-                    if (j < n) {
+                    for (int q = 0; q < 16; ++q) {
+                        const int j = p + G::P * q;
                         const cpx<T> y = buf[pad(a.bins[j])];
-                        const cpx<T> u = uf[l * n + j];
+                        const cpx<T> u = ul[j];
                         acc[q] += (double)(u.x * y.x - u.y * y.y);
+                    }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) {
+                        const int j = p + G::P * q;
+                        if (j < n) {
+                            const cpx<T> y = buf[pad(a.bins[j])];
+                            const cpx<T> u = ul[j];
+                            acc[q] += (double)(u.x * y.x - u.y * y.y);
+                        }
                     }
                 }
             }
@@ -456,12 +489,21 @@ __global__ void __launch_bounds__(Geo<LOG2L>::BLOCK == 64 ? 256 : Geo<LOG2L>::BL
             const bool keep = l0 < rank;
             const int l = keep ? l0 : rank - 1;
             sync_line<G::P>();  // previous users of buf are done
+            if (full) {
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int j = p + G::P * q;
-                if (j < n) {
+                for (int q = 0; q < 16; ++q) {
+                    const int j = p + G::P * q;
                     const cpx<T> u = uf[l * n + j];
                     buf[pad(j)] = {u.x * x[q], u.y * x[q]};
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int j = p + G::P * q;
+                    if (j < n) {
+                        const cpx<T> u = uf[l * n + j];
+                        buf[pad(j)] = {u.x * x[q], u.y * x[q]};
+                    }
                 }
             }
             sync_line<G::P>();

@@ -17,6 +17,7 @@ struct AxisLaunch {
     long long lines = 0;        // number of lines
     long long stride = 1;       // element stride along the axis
     int n = 0, L = 0, nu0 = 0, rank = 0;
+    int max_per_bin = 0;        // most nodes sharing one DFT bin
     int forward = 1;            // 1: W J alpha, 0: (W J)^T g
     int fp32 = 0;               // 0: fp64 arithmetic, 1: fp32 bulk (fp64 accumulation)
     // factor sections (device pointers inside the bound plan blob)
