@@ -274,8 +274,11 @@ struct QuadTables {
             gl_x[j] = xj;
             gl_w[j] = weight_at(r, 16, xj);  // Gauss-Legendre weights on [-1, 1]
         }
+        // The far-end singularity (ell - v)^e with e close to -1 leaves the
+        // transformed integrand decaying only like (1 - tau)^(1 + e); the
+        // range |y| <= 8.25 keeps that tail below 1e-20 for e >= -0.99.
         const ld h = 1.0L / 16;
-        const int K = 64;
+        const int K = 132;
         for (int k = -K; k <= K; ++k) {
             ld y = k * h;
             ld yp = kPi / 2 * sinhl(y);

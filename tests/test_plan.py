@@ -1,0 +1,290 @@
+"""Host plan (no GPU): nodes, weights, bins, direct block, companion function
+and the Algorithm 2.1 factorization, checked against the oracle and against
+facts the paper fixes.  Runs through the C ABI (libjt.so) only."""
+import math
+import os
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+import paper_1901_07275_amd as jt
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def plan1(n, a, b, tol, **kw):
+    return jt.Plan([n], [(a, b)], tol, **kw)
+
+
+# ---------------------------------------------------------------- nodes, weights
+@pytest.mark.parametrize("n,a,b", [(1, 0.2, 0.1), (2, -0.3, 0.4), (63, 0.3, -0.2), (64, 0.0, 0.0),
+                                   (1000, 0.25, -0.35), (1024, -0.4, 0.1), (4097, 0.45, -0.45),
+                                   (300, 0.9, -0.9), (200, -0.75, 0.6)])
+def test_nodes_and_weights_match_oracle(orc, n, a, b):
+    P = plan1(n, a, b, 1e-7)
+    t, x, w = P.nodes(0)
+    _, xo, wo = orc.matrix(n, a, b)
+    assert np.all(np.diff(t) > 0)
+    np.testing.assert_allclose(x, xo, rtol=0, atol=4e-16)
+    # weights at the end nodes, where 1 -+ x ~ 1/n^2, inherit the ~1e-19 absolute
+    # resolution of x in long double relative to 1 -+ x: allow 1e-12 relative
+    np.testing.assert_allclose(w, wo, rtol=1e-12, atol=0)
+    np.testing.assert_allclose(np.cos(t), x, rtol=0, atol=4e-16)
+
+
+@pytest.mark.parametrize("n,a,b", [(1024, 0.25, -0.35), (1000, 0.0, 0.0), (256, 0.3, 0.3)])
+def test_bins_follow_the_dft_grid(orc, n, a, b):
+    """m_j is the DFT frequency nearest to t_j L / 2 pi (eqs. (45), (47)), L = 2^p >= n."""
+    P = plan1(n, a, b, 1e-7)
+    bins, _, _, _ = P.factors(0)
+    L = P.info(0)["L"]
+    t = np.arccos(orc.matrix(n, a, b)[1])
+    s = t * L / (2 * np.pi)
+    exact = np.rint(s)
+    tie = np.abs(np.abs(s - np.floor(s)) - 0.5) < 1e-9
+    assert np.all((bins == exact) | tie)
+    assert bins.min() >= 0 and bins.max() <= L // 2
+    assert np.all(np.diff(bins) >= 0)
+
+
+def test_direct_block_matches_oracle_columns(orc):
+    n, a, b = 700, 0.25, -0.35
+    P = plan1(n, a, b, 1e-12)
+    _, wv, _, _ = P.factors(0)
+    A = orc.matrix(n, a, b)[0]
+    nu0 = P.info(0)["nu0"]
+    assert nu0 == 27
+    np.testing.assert_allclose(wv, A[:, :nu0].T, rtol=0, atol=2e-15)
+
+
+# ---------------------------------------------------------------- the identity J = [V, Re(B o F)]
+def test_low_rank_entries_reproduce_the_matrix(orc):
+    """Re(B_jk e^{+2 pi i m_j k / L}) equals the transform matrix entry for any companion
+    (eq. (46)); checks the exact entries the plan factorizes."""
+    n, a, b = 512, 0.25, -0.35
+    P = plan1(n, a, b, 1e-12)
+    bins, _, _, _ = P.factors(0)
+    L = P.info(0)["L"]
+    A = orc.matrix(n, a, b)[0]
+    rng = np.random.default_rng(0)
+    rows = rng.integers(0, n, 300)
+    degs = rng.integers(27, n, 300)
+    z = P.entries(0, rows, degs)
+    back = z * np.exp(2j * np.pi * ((bins[rows].astype(np.int64) * degs) % L) / L)
+    np.testing.assert_allclose(back.real, A[rows, degs], rtol=0, atol=1e-14)
+
+
+def test_companion_is_exact_for_chebyshev_first_kind():
+    """a = b = -1/2: Ptilde + i Qtilde = sqrt(2/pi) e^{ikt}, so the weighted entry is
+    sqrt(2/n) e^{ik t_j} before the DFT phase."""
+    n = 256
+    P = plan1(n, -0.5, -0.5, 1e-10)
+    t, _, _ = P.nodes(0)
+    bins, _, _, _ = P.factors(0)
+    L = P.info(0)["L"]
+    rng = np.random.default_rng(1)
+    rows = rng.integers(0, n, 200)
+    degs = rng.integers(27, n, 200)
+    z = P.entries(0, rows, degs) * np.exp(2j * np.pi * ((bins[rows].astype(np.int64) * degs) % L) / L)
+    np.testing.assert_allclose(z, np.sqrt(2.0 / n) * np.exp(1j * degs * t[rows]), rtol=0, atol=1e-14)
+
+
+def test_companion_is_exact_for_chebyshev_second_kind():
+    """a = b = +1/2: Ptilde + i Qtilde = -i sqrt(2/pi) e^{i(k+1)t}."""
+    n = 255
+    P = plan1(n, 0.5, 0.5, 1e-10)
+    t, _, _ = P.nodes(0)
+    bins, _, _, _ = P.factors(0)
+    L = P.info(0)["L"]
+    rng = np.random.default_rng(2)
+    rows = rng.integers(0, n, 200)
+    degs = rng.integers(27, n, 200)
+    z = P.entries(0, rows, degs) * np.exp(2j * np.pi * ((bins[rows].astype(np.int64) * degs) % L) / L)
+    ref = -1j * np.sqrt(2.0 / (n + 1)) * np.exp(1j * (degs + 1) * t[rows])
+    np.testing.assert_allclose(z, ref, rtol=0, atol=1e-14)
+
+
+def _mp_hilbert_qk(k, a, b, x, dps=25):
+    """q_k(x) = PV int (1-s)^a (1+s)^b phat_k(s) / (s - x) ds by mpmath quadrature,
+    with P_k from its explicit finite sum and the Gamma-function norm."""
+    with mp.workdps(dps):
+        a_, b_, x_ = mp.mpf(a), mp.mpf(b), mp.mpf(x)
+        coef = [mp.binomial(k + a_, k - i) * mp.binomial(k + b_, i) for i in range(k + 1)]
+        if k > 0:
+            h = (mp.power(2, a_ + b_ + 1) / (2 * k + a_ + b_ + 1) * mp.gamma(k + a_ + 1) * mp.gamma(k + b_ + 1)
+                 / (mp.gamma(k + a_ + b_ + 1) * mp.factorial(k)))
+        else:
+            h = mp.power(2, a_ + b_ + 1) * mp.gamma(a_ + 1) * mp.gamma(b_ + 1) / mp.gamma(a_ + b_ + 2)
+        rn = 1 / mp.sqrt(h)
+
+        def f(s):
+            xm, xp = (s - 1) / 2, (s + 1) / 2
+            poly = mp.fsum(c * xm ** i * xp ** (k - i) for i, c in enumerate(coef))
+            return (1 - s) ** a_ * (1 + s) ** b_ * poly * rn
+
+        fx = f(x_)
+        g = lambda s: (f(s) - fx) / (s - x_) if s != x_ else mp.mpf(0)
+        val = mp.quad(g, [-1, x_, 1]) + fx * mp.log((1 - x_) / (1 + x_))
+        return float(val), float((1 - x_) ** a_ * (1 + x_) ** b_)
+
+
+@pytest.mark.parametrize("a,b", [(0.25, -0.35), (0.0, 0.3), (-0.4, 0.0), (0.0, 0.0), (0.7, -0.6)])
+def test_companion_matches_quadrature(a, b):
+    """Im of the weighted entry is sqrt(omega_j) q_k(x_j) / (pi w(x_j)), q_k the finite
+    Hilbert transform of the weighted orthonormal polynomial (second-kind function)."""
+    n = 64
+    P = plan1(n, a, b, 1e-10, dense_below=1)
+    t, x, om = P.nodes(0)
+    bins, _, _, _ = P.factors(0)
+    L = P.info(0)["L"]
+    for j, k in ((3, 27), (20, 30), (40, 45), (60, 33)):
+        z = P.entries(0, [j], [k])[0] * np.exp(2j * np.pi * ((int(bins[j]) * k) % L) / L)
+        q, w = _mp_hilbert_qk(k, a, b, x[j])
+        ref = math.sqrt(om[j]) * q / (math.pi * w)
+        assert abs(z.imag - ref) <= 1e-12 * max(1.0, abs(ref)), (j, k, z.imag, ref)
+
+
+def _hilbert_weight_closed(x, a, b):
+    """PV int (1-s)^a (1+s)^b / (s - x) ds from Tricomi's closed form of the finite
+    Hilbert transform of the Jacobi weight:
+        pi cot(pi a) w(x) - 2^(a+b) Gamma(a) Gamma(b+1) / Gamma(a+b+1) 2F1(1, -a-b; 1-a; (1-x)/2),
+    with the reflection s -> -s when a = 0 and the Legendre logarithm when a = b = 0."""
+    x, a, b = mp.mpf(x), mp.mpf(a), mp.mpf(b)
+    if a == 0 and b == 0:
+        return mp.log((1 - x) / (1 + x))
+    if a == 0:
+        return -_hilbert_weight_closed(-x, b, a)
+    w = (1 - x) ** a * (1 + x) ** b
+    return (mp.pi * mp.cot(mp.pi * a) * w
+            - 2 ** (a + b) * mp.gamma(a) * mp.gamma(b + 1) * mp.rgamma(a + b + 1)
+            * mp.hyp2f1(1, -a - b, 1 - a, (1 - x) / 2))
+
+
+def _closed_qk(k, a, b, x):
+    """q_k(x) from the closed-form q_0 and the three-term recurrence of the orthonormal
+    Jacobi polynomials (with the extra sqrt(mu0) at k = 0 that the Hilbert transform
+    picks up), all in 40-digit arithmetic with explicit recurrence coefficients."""
+    with mp.workdps(40):
+        a_, b_, x_ = mp.mpf(a), mp.mpf(b), mp.mpf(x)
+        mu0 = 2 ** (a_ + b_ + 1) * mp.gamma(a_ + 1) * mp.gamma(b_ + 1) / mp.gamma(a_ + b_ + 2)
+
+        def alpha(j):
+            if j == 0:
+                return (b_ - a_) / (a_ + b_ + 2)
+            return (b_ * b_ - a_ * a_) / ((2 * j + a_ + b_) * (2 * j + a_ + b_ + 2))
+
+        def beta(j):
+            if j == 1:
+                return mp.sqrt(4 * (1 + a_) * (1 + b_) / ((a_ + b_ + 2) ** 2 * (a_ + b_ + 3)))
+            c = 2 * j + a_ + b_
+            return mp.sqrt(4 * j * (j + a_) * (j + b_) * (j + a_ + b_) / (c * c * (c + 1) * (c - 1)))
+
+        qm, q = mp.mpf(0), _hilbert_weight_closed(x_, a_, b_) / mp.sqrt(mu0)
+        for j in range(k):
+            qn = ((x_ - alpha(j)) * q - (beta(j) * qm if j else 0) + (mp.sqrt(mu0) if j == 0 else 0)) / beta(j + 1)
+            qm, q = q, qn
+        return q, (1 - x_) ** a_ * (1 + x_) ** b_
+
+
+@pytest.mark.parametrize("a,b", [(0.25, -0.35), (0.0, 0.3), (0.0, 0.0), (-0.9, -0.9), (-0.9, 0.2),
+                                 (0.3, -0.95), (0.9, 0.9), (-0.5, 0.5)])
+def test_companion_matches_closed_form(a, b):
+    """Same entries as above against Tricomi's closed form, including weights with
+    strong endpoint singularities (a or b near -1) where quadrature is delicate."""
+    n = 64
+    P = plan1(n, a, b, 1e-2, dense_below=1)
+    t, x, om = P.nodes(0)
+    bins, _, _, _ = P.factors(0)
+    L = P.info(0)["L"]
+    for j, k in ((0, 27), (3, 27), (20, 30), (32, 40), (60, 33), (63, 50)):
+        z = P.entries(0, [j], [k])[0] * np.exp(2j * np.pi * ((int(bins[j]) * k) % L) / L)
+        q, w = _closed_qk(k, a, b, x[j])
+        ref = float(mp.sqrt(om[j]) * q / (mp.pi * w))
+        assert abs(z.imag - ref) <= 1e-12 * max(1.0, abs(ref)), (j, k, z.imag, ref)
+
+
+# ---------------------------------------------------------------- Algorithm 2.1
+def _emulated_forward(P, axis, al):
+    bins, wv, U, V = P.factors(axis)
+    inf = P.info(axis)
+    n, nu0, L, r = inf["n"], inf["nu0"], inf["L"], inf["rank"]
+    out = wv.T @ al[:nu0]
+    for l in range(r):
+        xx = np.zeros(L, complex)
+        xx[nu0:n] = V[l] * al[nu0:]
+        y = np.fft.ifft(xx) * L
+        out = out + (U[l] * y[bins]).real
+    return out
+
+
+def _emulated_inverse(P, axis, g):
+    bins, wv, U, V = P.factors(axis)
+    inf = P.info(axis)
+    n, nu0, L, r = inf["n"], inf["nu0"], inf["L"], inf["rank"]
+    al = np.zeros(n)
+    al[:nu0] = wv @ g
+    for l in range(r):
+        z = np.zeros(L, complex)
+        np.add.at(z, bins, U[l] * g)
+        y = np.fft.ifft(z) * L
+        al[nu0:] += (V[l] * y[nu0:n]).real
+    return al
+
+
+@pytest.mark.parametrize("n,a,b,tol", [(1024, 0.25, -0.35, 1e-12), (1024, -0.4, 0.1, 1e-12),
+                                       (256, 0.3, 0.3, 1e-7), (777, 0.0, 0.0, 1e-9)])
+def test_factorization_applies_to_tolerance(orc, n, a, b, tol):
+    """The r-FFT formulas (eqs. (50), (51)), evaluated with numpy's FFT on the plan's
+    factors, reproduce the dense transform to the requested tolerance."""
+    P = plan1(n, a, b, tol)
+    inf = P.info(0)
+    assert inf["rel_err"] <= tol
+    A = orc.matrix(n, a, b)[0]
+    al = np.random.default_rng(n).standard_normal(n)
+    g = _emulated_forward(P, 0, al)
+    assert np.linalg.norm(g - A @ al) / np.linalg.norm(A @ al) <= 3 * tol
+    back = _emulated_inverse(P, 0, A @ al)
+    assert np.linalg.norm(back - al) / np.linalg.norm(al) <= 3 * tol
+
+
+def _golden_ranks():
+    rows = []
+    for line in open(os.path.join(GOLDEN, "rank_table_rs_n16384.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        ab, r = line.split()
+        rows.append((float(ab), int(r)))
+    return rows
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("ab,rank", _golden_ranks())
+def test_rank_matches_paper_table(ab, rank):
+    """At n = 2^14 and accuracy 1e-8 the ranks agree with the paper's RS column to
+    within 2 (the paper's error norm is not stated; ours is relative Frobenius)."""
+    P = plan1(16384, ab, ab, 1e-8)
+    got = P.info(0)["rank"]
+    assert abs(got - rank) <= 2, (ab, got, rank)
+
+
+def test_plan_is_deterministic():
+    p1 = plan1(500, 0.1, -0.2, 1e-9)
+    p2 = plan1(500, 0.1, -0.2, 1e-9)
+    for x1, x2 in zip(p1.factors(0), p2.factors(0)):
+        assert np.array_equal(x1, x2)
+    assert np.array_equal(p1.pack(), p2.pack())
+
+
+def test_dense_path_for_short_lines(orc):
+    P = plan1(40, 0.2, 0.1, 1e-12)
+    inf = P.info(0)
+    assert inf["rank"] == 0 and inf["nu0"] == 40
+    _, wv, _, _ = P.factors(0)
+    np.testing.assert_allclose(wv.T, orc.matrix(40, 0.2, 0.1)[0], rtol=0, atol=2e-15)
+
+
+def test_multi_axis_plan_keeps_axis_parameters():
+    P = jt.Plan([30, 70, 200], [(0.1, 0.2), (-0.3, 0.4), (0.45, -0.15)], 1e-9)
+    assert [P.info(i)["n"] for i in range(3)] == [30, 70, 200]
+    assert P.info(2)["L"] == 256 and P.info(1)["L"] == 128 and P.info(0)["L"] == 64
