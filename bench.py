@@ -11,6 +11,10 @@ gives per-launch durations for the roofline and per-step latencies for
 p50/p99.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+       python bench.py --workload batched-1d|batched-2d [--count 4096] [--steps K]
+The batched workloads time the persistent batch kernel (captured in a HIP
+graph) on ragged batches of independent transforms; they plan every item on
+the host first (untimed, several minutes for 4096 1D items).
 """
 from __future__ import annotations
 
@@ -100,6 +104,113 @@ def time_path(jt, torch, plan, alpha, prec, steps, warmup):
     return wall, step_ms, launch_ms, g, back
 
 
+def factor_bytes_fp32(info: dict, lines: int) -> float:
+    """Algorithmic HBM bytes of one fp32-bulk axis pass: the factors once
+    (u: r n, v: r L complex; direct block nu0 n; bins n; twiddles L) plus the
+    line data read and written once at the I/O dtype (counted by the caller)."""
+    n, L, r, nu0 = info["n"], info["L"], info["rank"], info["nu0"]
+    return 8.0 * r * n + 8.0 * r * L + 4.0 * nu0 * n + 4.0 * n + 8.0 * L
+
+
+def batched(args) -> int:
+    """The ragged batched form: `count` independent transforms in one
+    persistent launch (captured in a HIP graph), fp32 bulk, fp32 I/O."""
+    import torch
+
+    import paper_1901_07275_amd as jt
+
+    dev = torch.device("cuda:0")
+    if args.workload == "batched-1d":
+        items = workloads.batch_1d(args.count, seed=104)
+        shapes = [(n,) for n, _, _ in items]
+        abs_ = [(ab,) for _, ab, _ in items]
+    else:
+        items = workloads.batch_2d(args.count, seed=1041)
+        shapes = [n for n, _, _ in items]
+        abs_ = [ab for _, ab, _ in items]
+    xs = [x for _, _, x in items]
+    print("planning %d items" % len(items), file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    plans = jt.plan_many(shapes, abs_, 1e-7)
+    t_plan = time.perf_counter() - t0
+    print("planned in %.1f s" % t_plan, file=sys.stderr, flush=True)
+    arena = jt.PlanArena(plans, dev)
+    sizes = [int(np.prod(s)) for s in shapes]
+    offs = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(int)
+    coeffs = int(sum(sizes))
+    B = jt.Batch(plans, [jt.FORWARD] * len(plans), offs, offs, jt.F32, jt.F32, jt.PREC_FP32_BULK).bind(dev)
+    inp = torch.from_numpy(np.concatenate([x.ravel() for x in xs])).to(dev, torch.float32)
+    out = torch.empty_like(inp)
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(args.warmup):
+        B.run(inp, out)
+    torch.cuda.synchronize()
+    assert B.errors() == 0
+    B.capture(inp, out)
+    ms = []
+    for _ in range(args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        B.replay(stream)
+        e1.record(stream)
+        ms.append((e0, e1))
+    torch.cuda.synchronize()
+    ms = [a.elapsed_time(b) for a, b in ms]
+    t_ms = float(np.mean(ms))
+    # algorithmic bytes: every pass streams its factors once and its lines in and out (fp32)
+    nbytes = 0.0
+    for p, s in zip(plans, shapes):
+        total = int(np.prod(s))
+        for ax in range(p.d):
+            inf = p.info(ax)
+            nbytes += factor_bytes_fp32(inf, total // inf["n"]) + 8.0 * total
+    achieved = nbytes / (t_ms * 1e-3) / 1e9
+    # accuracy on a sample of items against the oracle (outside the timed region)
+    import oracle
+
+    got = out.double().cpu().numpy()
+    rng = np.random.default_rng(3)
+    small = [i for i, sz in enumerate(sizes) if sz <= 4096 * 8]
+    errs = []
+    for i in rng.choice(small, size=min(16, len(small)), replace=False):
+        x32 = xs[i].astype(np.float32).astype(np.float64)
+        ref = oracle.forward(x32, abs_[i])
+        g = got[offs[i]:offs[i] + sizes[i]].reshape(shapes[i])
+        errs.append(float(np.linalg.norm(g - ref) / np.linalg.norm(ref)))
+    # the plain fp64 path on the same GPU: the same items one transform at a time
+    dev_x = [torch.from_numpy(x).to(dev) for x in xs]
+    dev_g = [torch.empty_like(x) for x in dev_x]
+    for p, x, g in zip(plans, dev_x, dev_g):
+        p.forward(x, g, prec=jt.PREC_FP64)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for p, x, g in zip(plans, dev_x, dev_g):
+        p.forward(x, g, prec=jt.PREC_FP64)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t64 = e0.elapsed_time(e1)
+    info = B.info()
+    line = {
+        "metric": "coeffs/s, ragged batch of %d independent %s transforms in one persistent launch"
+                  % (len(items), "1D" if args.workload == "batched-1d" else "2D"),
+        "value": coeffs / (t_ms * 1e-3), "unit": "coeffs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": t_ms, "p50_ms": percentile(ms, 50), "p99_ms": percentile(ms, 99),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "items": len(items), "coeffs": coeffs, "tol": 1e-7,
+                   "units": info["units"], "grid": info["grid"], "threads": info["threads"],
+                   "plan_seconds": t_plan, "graph": True},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
+                     "frac": achieved / 8000.0, "traffic": None, "kernel": "batch_kernel<float>",
+                     "bytes_per_launch": nbytes},
+        "sample_rel_l2_max": max(errs) if errs else None,
+        "fp64_one_at_a_time": {"ms": t64, "value": coeffs / (t64 * 1e-3), "launches": int(sum(len(s) for s in shapes))},
+    }
+    print(json.dumps(line))
+    del arena
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +218,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--workload", default="2d", choices=["2d", "batched-1d", "batched-2d"],
+                    help="2d: the 1024 x 1024 forward + inverse headline; batched-*: ragged batches")
+    ap.add_argument("--count", type=int, default=4096, help="items of a batched workload")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times), to calibrate "
                          "rocprofv3 FETCH_SIZE/WRITE_SIZE against known bytes")
@@ -127,6 +241,9 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": nbytes, "launches": 5}))
         return 0
+
+    if args.workload != "2d":
+        return batched(args)
 
     import paper_1901_07275_amd as jt
 

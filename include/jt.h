@@ -178,6 +178,80 @@ jt_status jt_inverse(jt_plan_t plan, const void *g_dev, jt_dtype in, void *alpha
 jt_status jt_apply_axis(jt_plan_t plan, int axis, jt_direction dir, const void *in_dev, jt_dtype in,
                         void *out_dev, jt_dtype out, jt_prec prec, void *stream);
 
+/* ----------------------------------------------------------------------
+ * Many plans at once.  Builds `count` plans on the host, one host thread per
+ * plan (the plans of a batch of independent transforms, Section 3 applied to
+ * each item).
+ *   dims   : count entries in {1, 2, 3}
+ *   n, a, b: the items' axis parameters concatenated (sum of dims entries);
+ *            item i uses entries s_i .. s_i + dims[i] - 1, s_i = dims[0] + ... + dims[i-1]
+ *   tol    : as jt_plan (one tolerance for the whole batch)
+ *   opt    : NULL, or count option structs (one per item)
+ *   plans  : receives count handles (each freed with jt_plan_destroy)
+ * On error no handle is returned (all are freed) and jt_last_error names the item.
+ */
+jt_status jt_plan_many(int count, const int *dims, const int *n, const double *a, const double *b,
+                       double tol, const jt_plan_options *opt, jt_plan_t *plans);
+
+/* ----------------------------------------------------------------------
+ * Batched form: many independent transforms (uneven n, d, (a, b); forward or
+ * inverse) in ONE persistent kernel launch that takes work units from a
+ * device queue.  Every axis pass of every item is cut into units of a few
+ * lines; a block takes the next unit from an atomic head counter; a unit of
+ * an item's later pass waits (bounded, on a device counter) for that item's
+ * previous pass.  The unit table lives in a caller-owned device buffer.
+ */
+typedef struct jt_batch_s *jt_batch_t;
+
+typedef struct {
+    int max_split;     /* largest rank split S (groups sharing a line set); 0 = 16 */
+    int min_units;     /* raise S until a pass has at least this many units; 0 = 1 */
+    int grid;          /* persistent blocks; 0 = one per compute unit */
+} jt_batch_options;
+
+typedef struct {
+    int units;         /* work units in the queue */
+    int passes;        /* axis passes (sum of item dims) */
+    int grid;          /* blocks of the persistent launch */
+    int threads;       /* threads per block (1024 for fp32, 512 for fp64) */
+    size_t lds_bytes;  /* dynamic LDS per block */
+    double cost;       /* estimated work (arbitrary units) of the whole queue */
+} jt_batch_info;
+
+/*
+ * Describe a batch.  Item i applies plans[i] in direction dirs[i] to the
+ * tensor at byte offset in_off[i] of the run's input buffer, writing byte
+ * offset out_off[i] of the output buffer (the two may coincide when in == out).
+ * All items share the dtypes and the precision.  The plans must outlive the
+ * batch and be bound (jt_plan_bind) before jt_batch_bind.  opt may be NULL.
+ * Errors: JT_EINVAL, JT_EUNSUPPORTED (fp64 with n > 8192), JT_ENOMEM.
+ */
+jt_status jt_batch_create(int count, const jt_plan_t *plans, const int *dirs, const uint64_t *in_off,
+                          const uint64_t *out_off, jt_dtype in, jt_dtype out, jt_prec prec,
+                          const jt_batch_options *opt, jt_batch_t *batch);
+jt_status jt_batch_destroy(jt_batch_t batch);
+jt_status jt_batch_info_get(jt_batch_t batch, jt_batch_info *info);
+/* Host copy of the unit table in queue order: 6 int32 per unit
+ * (pass, first line, lines, split S, pass waited for or -1, units waited for),
+ * and of the pass table: 4 int32 per pass (item, axis, lines, units).
+ * Either pointer may be NULL. */
+jt_status jt_batch_tables(jt_batch_t batch, int32_t *units, int32_t *passes);
+/* Device bytes the batch needs (unit table, pass table, counters). */
+jt_status jt_batch_device_bytes(jt_batch_t batch, size_t *bytes);
+/* Copy the tables into dev_buf (256-byte aligned, >= jt_batch_device_bytes);
+ * synchronises `stream`.  Errors: JT_ESTATE (a plan is not bound), JT_ENOMEM, JT_EDEVICE. */
+jt_status jt_batch_bind(jt_batch_t batch, void *dev_buf, size_t bytes, void *stream);
+/* Run every item: one counter-clearing kernel and the persistent kernel on
+ * `stream`, no host synchronisation.  Runs of one batch must not overlap. */
+jt_status jt_batch_run(jt_batch_t batch, const void *in_base, void *out_base, void *stream);
+/* Capture jt_batch_run(in_base, out_base) into a HIP graph held by the batch
+ * (replaces an earlier capture); jt_batch_replay launches it on `stream`. */
+jt_status jt_batch_capture(jt_batch_t batch, const void *in_base, void *out_base);
+jt_status jt_batch_replay(jt_batch_t batch, void *stream);
+/* Error word of the last run (synchronises `stream`): bit 0 = a unit's wait
+ * for its previous pass timed out, bit 1 = unsupported length. 0 = clean. */
+jt_status jt_batch_errors(jt_batch_t batch, void *stream, uint32_t *flags);
+
 /* Message describing the last error on the calling thread ("" if none). */
 const char *jt_last_error(void);
 

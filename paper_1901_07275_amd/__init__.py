@@ -42,6 +42,15 @@ class AxisInfo(ctypes.Structure):
                 ("rel_err", ctypes.c_double), ("fro", ctypes.c_double)]
 
 
+class BatchOptions(ctypes.Structure):
+    _fields_ = [("max_split", ctypes.c_int), ("min_units", ctypes.c_int), ("grid", ctypes.c_int)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("units", ctypes.c_int), ("passes", ctypes.c_int), ("grid", ctypes.c_int),
+                ("threads", ctypes.c_int), ("lds_bytes", ctypes.c_size_t), ("cost", ctypes.c_double)]
+
+
 _vp = ctypes.c_void_p
 _ip = ctypes.POINTER(ctypes.c_int)
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -66,6 +75,18 @@ SYMBOLS = {
     "jt_inverse": [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp],
     "jt_apply_axis": [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int,
                       _vp],
+    "jt_plan_many": [ctypes.c_int, _ip, _ip, _dp, _dp, ctypes.c_double, ctypes.POINTER(PlanOptions), _vp],
+    "jt_batch_create": [ctypes.c_int, _vp, _ip, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
+                        ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(BatchOptions), ctypes.POINTER(_vp)],
+    "jt_batch_destroy": [_vp],
+    "jt_batch_info_get": [_vp, ctypes.POINTER(BatchInfo)],
+    "jt_batch_tables": [_vp, _i32p, _i32p],
+    "jt_batch_device_bytes": [_vp, ctypes.POINTER(ctypes.c_size_t)],
+    "jt_batch_bind": [_vp, _vp, ctypes.c_size_t, _vp],
+    "jt_batch_run": [_vp, _vp, _vp, _vp],
+    "jt_batch_capture": [_vp, _vp, _vp],
+    "jt_batch_replay": [_vp, _vp],
+    "jt_batch_errors": [_vp, _vp, ctypes.POINTER(ctypes.c_uint32)],
 }
 for _name, _args in SYMBOLS.items():
     _f = getattr(_lib, _name)
@@ -119,6 +140,17 @@ class Plan:
         _check(_lib.jt_plan_ex(d, nn, aa, bb, self.tol, ctypes.byref(opt), ctypes.byref(h)))
         self._h = h
         self._dev = None
+
+    @classmethod
+    def _adopt(cls, handle, n, ab, tol):
+        """Wrap a plan handle built by the library (jt_plan_many)."""
+        self = cls.__new__(cls)
+        self.n = tuple(int(v) for v in n)
+        self.ab = tuple((float(a), float(b)) for a, b in ab)
+        self.tol = float(tol)
+        self._h = _vp(handle)
+        self._dev = None
+        return self
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -243,3 +275,151 @@ class Plan:
                                   _vp(out.data_ptr()), self._dtype_code(out), int(prec),
                                   _vp(st.cuda_stream)))
         return out
+
+
+# ---------------------------------------------------------------- many plans, batches
+def plan_many(shapes, abs_, tol: float, dense_below=None):
+    """Build one plan per item on the host, one host thread per plan.
+
+    shapes: per item a tuple of sizes (d = 1..3); abs_: per item a tuple of (a, b)
+    pairs; dense_below: None, or per item the dense-path threshold (the
+    FFT-vs-direct crossover)."""
+    count = len(shapes)
+    dims = [len(s) for s in shapes]
+    flat_n = [int(v) for s in shapes for v in s]
+    flat_a = [float(p[0]) for ab in abs_ for p in ab]
+    flat_b = [float(p[1]) for ab in abs_ for p in ab]
+    if len(flat_a) != len(flat_n):
+        raise ValueError("need one (a, b) pair per axis of every item")
+    handles = (_vp * count)()
+    opts = None
+    if dense_below is not None:
+        arr = (PlanOptions * count)()
+        for i, db in enumerate(dense_below):
+            arr[i].dense_below = int(db)
+        opts = arr
+    _check(_lib.jt_plan_many(count, (ctypes.c_int * count)(*dims), (ctypes.c_int * len(flat_n))(*flat_n),
+                             (ctypes.c_double * len(flat_a))(*flat_a), (ctypes.c_double * len(flat_b))(*flat_b),
+                             float(tol), opts, ctypes.cast(handles, _vp)))
+    return [Plan._adopt(handles[i], shapes[i], abs_[i], tol) for i in range(count)]
+
+
+class PlanArena:
+    """One device buffer holding the bound factors of many plans."""
+
+    def __init__(self, plans, device=None, stream=None):
+        import torch
+
+        device = torch.device(device or "cuda")
+        offs, total = [], 0
+        for p in plans:
+            offs.append(total)
+            total += (p.device_bytes() + 255) // 256 * 256
+        self.buf = torch.empty(total + 256, dtype=torch.uint8, device=device)
+        base = self.buf.data_ptr() + (-self.buf.data_ptr()) % 256
+        st = stream if stream is not None else torch.cuda.current_stream(device)
+        for p, o in zip(plans, offs):
+            _check(_lib.jt_plan_bind(p._h, _vp(base + o), p.device_bytes(), _vp(st.cuda_stream)))
+            p._dev = self.buf
+        self.bytes = total
+
+
+class Batch:
+    """Many independent transforms in one persistent launch (jt_batch_*).
+
+    plans: bound plans; dirs: FORWARD/INVERSE per item; in_offsets/out_offsets:
+    element offsets of each item's tensor in the flat input/output buffers
+    passed to run(); in_dtype/out_dtype: F64 or F32; prec: PREC_*."""
+
+    def __init__(self, plans, dirs, in_offsets, out_offsets, in_dtype=F64, out_dtype=F64, prec=PREC_FP32_BULK,
+                 max_split=0, min_units=0, grid=0):
+        count = len(plans)
+        self.plans = list(plans)  # keep the plans alive
+        isz = 8 if in_dtype == F64 else 4
+        osz = 8 if out_dtype == F64 else 4
+        hs = (_vp * count)(*[p._h.value for p in plans])
+        ioff = (ctypes.c_uint64 * count)(*[int(o) * isz for o in in_offsets])
+        ooff = (ctypes.c_uint64 * count)(*[int(o) * osz for o in out_offsets])
+        opt = BatchOptions(int(max_split), int(min_units), int(grid))
+        h = _vp()
+        _check(_lib.jt_batch_create(count, ctypes.cast(hs, _vp), (ctypes.c_int * count)(*[int(d) for d in dirs]),
+                                    ioff, ooff, int(in_dtype), int(out_dtype), int(prec), ctypes.byref(opt),
+                                    ctypes.byref(h)))
+        self._h = h
+        self._dev = None
+        self.in_dtype, self.out_dtype = in_dtype, out_dtype
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.jt_batch_destroy(h)
+            self._h = None
+
+    def info(self) -> dict:
+        inf = BatchInfo()
+        _check(_lib.jt_batch_info_get(self._h, ctypes.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in BatchInfo._fields_}
+
+    def tables(self):
+        """(units: (U, 6) int32 in queue order, passes: (P, 4) int32)."""
+        inf = self.info()
+        u = np.empty((inf["units"], 6), dtype=np.int32)
+        p = np.empty((inf["passes"], 4), dtype=np.int32)
+        _check(_lib.jt_batch_tables(self._h, u.ctypes.data_as(_i32p), p.ctypes.data_as(_i32p)))
+        return u, p
+
+    def device_bytes(self) -> int:
+        b = ctypes.c_size_t()
+        _check(_lib.jt_batch_device_bytes(self._h, ctypes.byref(b)))
+        return b.value
+
+    def bind(self, device=None, stream=None):
+        import torch
+
+        device = torch.device(device or "cuda")
+        nbytes = self.device_bytes()
+        buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        off = (-buf.data_ptr()) % 256
+        st = stream if stream is not None else torch.cuda.current_stream(device)
+        _check(_lib.jt_batch_bind(self._h, _vp(buf.data_ptr() + off), nbytes, _vp(st.cuda_stream)))
+        self._dev = buf
+        return self
+
+    def _bufs(self, inp, out):
+        import torch
+
+        want_in = torch.float64 if self.in_dtype == F64 else torch.float32
+        want_out = torch.float64 if self.out_dtype == F64 else torch.float32
+        if not (isinstance(inp, torch.Tensor) and inp.is_cuda and inp.dtype == want_in and inp.is_contiguous()):
+            raise TypeError("input must be a contiguous CUDA tensor of dtype %s" % want_in)
+        if not (isinstance(out, torch.Tensor) and out.is_cuda and out.dtype == want_out and out.is_contiguous()):
+            raise TypeError("output must be a contiguous CUDA tensor of dtype %s" % want_out)
+        return _vp(inp.data_ptr()), _vp(out.data_ptr())
+
+    def run(self, inp, out, stream=None):
+        import torch
+
+        i, o = self._bufs(inp, out)
+        st = stream if stream is not None else torch.cuda.current_stream(inp.device)
+        _check(_lib.jt_batch_run(self._h, i, o, _vp(st.cuda_stream)))
+        return out
+
+    def capture(self, inp, out):
+        i, o = self._bufs(inp, out)
+        self._graph_bufs = (inp, out)
+        _check(_lib.jt_batch_capture(self._h, i, o))
+        return self
+
+    def replay(self, stream=None):
+        import torch
+
+        st = stream if stream is not None else torch.cuda.current_stream(self._graph_bufs[0].device)
+        _check(_lib.jt_batch_replay(self._h, _vp(st.cuda_stream)))
+
+    def errors(self, stream=None) -> int:
+        import torch
+
+        st = stream if stream is not None else torch.cuda.current_stream()
+        v = ctypes.c_uint32()
+        _check(_lib.jt_batch_errors(self._h, _vp(st.cuda_stream), ctypes.byref(v)))
+        return v.value

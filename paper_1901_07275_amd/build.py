@@ -24,7 +24,7 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wn
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics"]
 
-SOURCES = ["plan.cpp", "dense.cpp", "api.cpp", "axis_pass.hip"]
+SOURCES = ["plan.cpp", "dense.cpp", "api.cpp", "batch_api.cpp", "axis_pass.hip", "batch.hip"]
 
 
 def _compile(src: str) -> str:
@@ -34,7 +34,8 @@ def _compile(src: str) -> str:
     if src.endswith(".hip"):
         cmd = [HIPCC, "-x", "hip"] + COMMON + DEVICE + ["-c", path, "-o", obj]
     else:
-        cmd = [HIPCC, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include"] + COMMON + ["-c", path, "-o", obj]
+        cmd = ([HIPCC, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include"] + COMMON
+               + ["-fcx-limited-range", "-c", path, "-o", obj])
     subprocess.check_call(cmd)
     return obj
 

@@ -10,50 +10,16 @@
 #include <string>
 #include <vector>
 
+#include "handle.h"
 #include "launch.h"
 #include "plan.h"
 
-struct jt_plan_s {
-    int d = 0;
-    jt::AxisPlan ax[3];
-    std::vector<unsigned char> blob;  // packed device image
-    size_t dev_bytes = 0;
-    unsigned char *dev = nullptr;     // caller-owned device buffer (after bind)
-};
-
 namespace {
 
-thread_local std::string g_err;
-
-jt_status fail(jt_status st, const std::string &msg)
-{
-    g_err = msg;
-    return st;
-}
-
-jt_status ok()
-{
-    g_err.clear();
-    return JT_OK;
-}
-
-template <class F>
-jt_status guarded(F f)
-{
-    try {
-        return f();
-    } catch (const std::invalid_argument &e) {
-        return fail(JT_EINVAL, e.what());
-    } catch (const std::bad_alloc &) {
-        return fail(JT_ENOMEM, "host allocation failed");
-    } catch (const std::runtime_error &e) {
-        return fail(JT_ENOTCONV, e.what());
-    } catch (const std::exception &e) {
-        return fail(JT_EINVAL, e.what());
-    } catch (...) {
-        return fail(JT_EINVAL, "unknown error");
-    }
-}
+using jt::fail;
+using jt::ok;
+using jt::guarded;
+using jt::g_err;
 
 jt_status check_axis(jt_plan_t p, int axis)
 {
@@ -129,9 +95,47 @@ jt_status run_all(jt_plan_t p, bool forward, const void *in, jt_dtype tin, void 
 
 }  // namespace
 
+namespace jt {
+
+PlanOptions plan_options(const jt_plan_options *opt)
+{
+    PlanOptions po;
+    if (opt) {
+        if (opt->nu0 > 0) po.nu0 = opt->nu0;
+        if (opt->dense_below >= 0) po.dense_below = opt->dense_below;
+        if (opt->oversample > 0) po.oversample = opt->oversample;
+        if (opt->iterations > 0) po.iterations = opt->iterations;
+        po.seed = opt->seed;
+    }
+    return po;
+}
+
+jt_plan_s *build_plan(int d, const int *n, const double *a, const double *b, double tol, const PlanOptions &po)
+{
+    if (d < 1 || d > 3) throw std::invalid_argument("d must be 1, 2 or 3");
+    jt_plan_s *p = new jt_plan_s();
+    try {
+        p->d = d;
+        size_t off = 0;
+        for (int i = 0; i < d; ++i) {
+            build_axis(p->ax[i], n[i], a[i], b[i], tol, po);
+            off = layout_axis(p->ax[i], off);
+        }
+        p->dev_bytes = off;
+        p->blob.assign(off, 0);
+        for (int i = 0; i < d; ++i) pack_axis(p->ax[i], p->blob.data());
+    } catch (...) {
+        delete p;
+        throw;
+    }
+    return p;
+}
+
+}  // namespace jt
+
 extern "C" {
 
-int jt_version(void) { return 100; }
+int jt_version(void) { return 110; }
 
 const char *jt_last_error(void) { return g_err.c_str(); }
 
@@ -143,30 +147,7 @@ jt_status jt_plan_ex(int d, const int *n, const double *a, const double *b, doub
         *out = nullptr;
         if (d < 1 || d > 3) return fail(JT_EINVAL, "d must be 1, 2 or 3");
         if (!n || !a || !b) return fail(JT_EINVAL, "null parameter array");
-        jt::PlanOptions po;
-        if (opt) {
-            if (opt->nu0 > 0) po.nu0 = opt->nu0;
-            if (opt->dense_below >= 0) po.dense_below = opt->dense_below;
-            if (opt->oversample > 0) po.oversample = opt->oversample;
-            if (opt->iterations > 0) po.iterations = opt->iterations;
-            po.seed = opt->seed;
-        }
-        jt_plan_s *p = new jt_plan_s();
-        try {
-            p->d = d;
-            size_t off = 0;
-            for (int i = 0; i < d; ++i) {
-                jt::build_axis(p->ax[i], n[i], a[i], b[i], tol, po);
-                off = jt::layout_axis(p->ax[i], off);
-            }
-            p->dev_bytes = off;
-            p->blob.assign(off, 0);
-            for (int i = 0; i < d; ++i) jt::pack_axis(p->ax[i], p->blob.data());
-        } catch (...) {
-            delete p;
-            throw;
-        }
-        *out = p;
+        *out = jt::build_plan(d, n, a, b, tol, jt::plan_options(opt));
         return ok();
     });
 }

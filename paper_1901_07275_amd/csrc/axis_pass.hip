@@ -26,293 +26,12 @@
 
 #include "launch.h"
 
+#include "fft_line.h"
+
 namespace jt {
 namespace {
 
-template <class T>
-struct cpx {
-    T x, y;
-};
-
-template <class T>
-__device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) { return {a.x + b.x, a.y + b.y}; }
-template <class T>
-__device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) { return {a.x - b.x, a.y - b.y}; }
-template <class T>
-__device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b)
-{
-    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
-}
-template <class T>
-__device__ __forceinline__ cpx<T> muli(cpx<T> a) { return {-a.y, a.x}; }
-
-// exp(2 pi i e / 16) for e = 0..15
-constexpr double kW16c[16] = {
-    1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
-    0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
-    -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173,
-    0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613};
-constexpr double kW16s[16] = {
-    0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613,
-    1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
-    0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
-    -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173};
-
-template <class T, int E>
-__device__ __forceinline__ cpx<T> w16(cpx<T> a)
-{
-    constexpr int e = E & 15;
-    if constexpr (e == 0) {
-        return a;
-    } else if constexpr (e == 4) {
-        return {-a.y, a.x};
-    } else if constexpr (e == 8) {
-        return {-a.x, -a.y};
-    } else if constexpr (e == 12) {
-        return {a.y, -a.x};
-    } else if constexpr (e == 2 || e == 6 || e == 10 || e == 14) {
-        // (c, s) with |c| = |s| = sqrt(2)/2
-        constexpr T r = (T)0.70710678118654752440;
-        constexpr T cs = (e == 2 || e == 14) ? r : -r;
-        constexpr T sn = (e == 2 || e == 6) ? r : -r;
-        return {cs * a.x - sn * a.y, sn * a.x + cs * a.y};
-    } else {
-        constexpr T c = (T)kW16c[e], s = (T)kW16s[e];
-        return {c * a.x - s * a.y, s * a.x + c * a.y};
-    }
-}
-
-template <class T>
-__device__ __forceinline__ void dft2(cpx<T> &a0, cpx<T> &a1)
-{
-    cpx<T> t = a0;
-    a0 = t + a1;
-    a1 = t - a1;
-}
-
-// sign +:  X_m = sum_k a_k i^{k m}
-template <class T>
-__device__ __forceinline__ void dft4(cpx<T> &a0, cpx<T> &a1, cpx<T> &a2, cpx<T> &a3)
-{
-    cpx<T> t0 = a0 + a2, t1 = a0 - a2, t2 = a1 + a3, t3 = muli(a1 - a3);
-    a0 = t0 + t2;
-    a2 = t0 - t2;
-    a1 = t1 + t3;
-    a3 = t1 - t3;
-}
-
-// In-place 8-point DFT (sign +), natural order in and out: 8 = 2 x 4.
-template <class T>
-__device__ __forceinline__ void dft8(cpx<T> *v)
-{
-    // k = k1 + 2 k2:  4-point DFTs over k2 for k1 = 0, 1
-    dft4(v[0], v[2], v[4], v[6]);
-    dft4(v[1], v[3], v[5], v[7]);
-    // twiddle omega_8^{k1 m2} = omega_16^{2 k1 m2}
-    v[3] = w16<T, 2>(v[3]);
-    v[5] = w16<T, 4>(v[5]);
-    v[7] = w16<T, 6>(v[7]);
-    // X[m2 + 4 m1] = 2-point DFT over k1 of Y[k1][m2] (stored at v[k1 + 2 m2])
-    cpx<T> o[8];
-#pragma unroll
-    for (int m2 = 0; m2 < 4; ++m2) {
-        cpx<T> a = v[2 * m2], b = v[2 * m2 + 1];
-        o[m2] = a + b;
-        o[m2 + 4] = a - b;
-    }
-#pragma unroll
-    for (int i = 0; i < 8; ++i) v[i] = o[i];
-}
-
-// In-place 16-point DFT (sign +), natural order in and out: 16 = 4 x 4.
-template <class T>
-__device__ __forceinline__ void dft16(cpx<T> *v)
-{
-#pragma unroll
-    for (int k1 = 0; k1 < 4; ++k1) dft4(v[k1], v[k1 + 4], v[k1 + 8], v[k1 + 12]);
-    v[5] = w16<T, 1>(v[5]);
-    v[9] = w16<T, 2>(v[9]);
-    v[13] = w16<T, 3>(v[13]);
-    v[6] = w16<T, 2>(v[6]);
-    v[10] = w16<T, 4>(v[10]);
-    v[14] = w16<T, 6>(v[14]);
-    v[7] = w16<T, 3>(v[7]);
-    v[11] = w16<T, 6>(v[11]);
-    v[15] = w16<T, 9>(v[15]);
-    cpx<T> o[16];
-#pragma unroll
-    for (int m2 = 0; m2 < 4; ++m2) {
-        cpx<T> a0 = v[4 * m2], a1 = v[4 * m2 + 1], a2 = v[4 * m2 + 2], a3 = v[4 * m2 + 3];
-        dft4(a0, a1, a2, a3);
-        o[m2] = a0;
-        o[m2 + 4] = a1;
-        o[m2 + 8] = a2;
-        o[m2 + 12] = a3;
-    }
-#pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = o[i];
-}
-
-template <class T, int R>
-__device__ __forceinline__ void dftR(cpx<T> *v)
-{
-    if constexpr (R == 2) dft2(v[0], v[1]);
-    else if constexpr (R == 4) dft4(v[0], v[1], v[2], v[3]);
-    else if constexpr (R == 8) dft8(v);
-    else dft16(v);
-}
-
-// Synchronisation of the lanes that share one line buffer.  A line of up to
-// 1024 points lives in one wave: its lanes exchange data through LDS in
-// program order, so a wave-scope fence (no instruction, it only stops the
-// compiler from moving LDS accesses across it) is enough, and the other waves
-// of the block keep running.  Longer lines span several waves and need the
-// block barrier.
-template <int P>
-__device__ __forceinline__ void sync_line()
-{
-    if constexpr (P <= 64) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    } else {
-        __syncthreads();
-    }
-}
-
-// padded LDS index: one spare slot every 16 elements
-__device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
-
-template <int LOG2L>
-struct Geo {
-    static constexpr int L = 1 << LOG2L;
-    static constexpr int P = L / 16;                 // lanes per line
-    static constexpr int S16 = LOG2L / 4;            // radix-16 passes
-    static constexpr int F = LOG2L % 4;
-    static constexpr int RF = 1 << F;                // final radix (1: none)
-    static constexpr int NMID = S16 - 1;             // radix-16 passes after the first
-    static constexpr int BLOCK = (P < 64) ? 64 : P;  // threads per block
-    static constexpr int LPB = BLOCK / P;            // lines per block
-    static constexpr int BUF = L + L / 16;           // padded line buffer (complex)
-};
-
-// Twiddles of all passes after the first.  They depend only on the lane, so
-// the fp32 kernels keep them in registers for the whole kernel; the fp64
-// kernels (twice the register cost) and blocks of 512+ threads read them from
-// the L-entry table when a pass needs them.
-// Where the per-pass twiddles live: 0 = registers (loaded once), 1 = a copy
-// of the table in LDS (loaded once per block), 2 = the table in global memory
-// (L1/L2 resident).  Measured on the 1024-point lines, 2 is fastest in both
-// precisions: registers are better spent on occupancy.
-#ifndef JT_TW_MODE_F32
-#define JT_TW_MODE_F32 2
-#endif
-#ifndef JT_TW_MODE_F64
-#define JT_TW_MODE_F64 2
-#endif
-template <class T, int LOG2L>
-constexpr int tw_mode()
-{
-    if constexpr (Geo<LOG2L>::BLOCK > 256) return 2;  // big lines: too few registers per lane
-    else return sizeof(T) == 4 ? JT_TW_MODE_F32 : JT_TW_MODE_F64;
-}
-
-template <class T, int LOG2L>
-struct Twiddles {
-    using G = Geo<LOG2L>;
-    static constexpr bool kHoist = tw_mode<T, LOG2L>() == 0;
-    cpx<T> mid_[(kHoist && G::NMID > 0) ? G::NMID : 1][15];
-    cpx<T> fin_[(kHoist && G::RF > 1) ? 16 / G::RF : 1][(G::RF > 1) ? G::RF - 1 : 1];
-    const cpx<T> *tw;
-    int p;
-
-    // pass i+1 has Ns = 16^(i+1); factor omega_{16 Ns}^{(p mod Ns) r} = tw[(p mod Ns) r L / (16 Ns)]
-    static __device__ __forceinline__ int mid_index(int i, int r, int p)
-    {
-        int ns = 16;
-        for (int k = 0; k < i; ++k) ns *= 16;
-        return (p & (ns - 1)) * r * (G::L / (16 * ns));
-    }
-    // final pass (radix RF, Ns = L/RF): task j = p + P t, factor omega_L^{j r}
-    static __device__ __forceinline__ int fin_index(int t, int r, int p) { return (p + G::P * t) * r; }
-
-    __device__ __forceinline__ void load(const cpx<T> *table, int lane)
-    {
-        tw = table;
-        p = lane;
-        if constexpr (kHoist) {
-#pragma unroll
-            for (int i = 0; i < G::NMID; ++i)
-#pragma unroll
-                for (int r = 1; r < 16; ++r) mid_[i][r - 1] = tw[mid_index(i, r, p)];
-            if constexpr (G::RF > 1) {
-#pragma unroll
-                for (int t = 0; t < 16 / G::RF; ++t)
-#pragma unroll
-                    for (int r = 1; r < G::RF; ++r) fin_[t][r - 1] = tw[fin_index(t, r, p)];
-            }
-        }
-    }
-    __device__ __forceinline__ cpx<T> mid(int i, int r) const
-    {
-        if constexpr (kHoist) return mid_[i][r - 1];
-        else return tw[mid_index(i, r, p)];
-    }
-    __device__ __forceinline__ cpx<T> fin(int t, int r) const
-    {
-        if constexpr (kHoist) return fin_[t][r - 1];
-        else return tw[fin_index(t, r, p)];
-    }
-};
-
-// L-point DFT (sign +) of the line held in v (lane-owned layout, v[q] = x[p + P q]);
-// on return v[q] = X[p + P q].  buf is this line's LDS buffer.  Every thread of
-// the block must call it (it contains block barriers).
-template <class T, int LOG2L>
-__device__ __forceinline__ void fft_line(cpx<T> *v, cpx<T> *buf, int p, const Twiddles<T, LOG2L> &tw)
-{
-    using G = Geo<LOG2L>;
-    static_assert(G::L >= 64, "lines shorter than 64 use the dense path with L = 64");
-    // pass 0: Ns = 1, no twiddles, inputs are already v[r] = x[p + r P]
-    dft16(v);
-#pragma unroll
-    for (int r = 0; r < 16; ++r) buf[pad(p * 16 + r)] = v[r];
-    int ns = 16;
-#pragma unroll
-    for (int i = 0; i < G::NMID; ++i) {
-        sync_line<G::P>();
-#pragma unroll
-        for (int r = 0; r < 16; ++r) v[r] = buf[pad(p + r * G::P)];
-#pragma unroll
-        for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], tw.mid(i, r));
-        dft16(v);
-        const bool last = (G::RF == 1) && (i == G::NMID - 1);
-        if (!last) {
-            sync_line<G::P>();
-            const int base = (p / ns) * ns * 16 + (p & (ns - 1));
-#pragma unroll
-            for (int r = 0; r < 16; ++r) buf[pad(base + r * ns)] = v[r];
-        }
-        ns *= 16;
-    }
-    if constexpr (G::RF > 1) {
-        constexpr int RF = G::RF, NT = 16 / RF;
-        sync_line<G::P>();
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            cpx<T> w[RF];
-            const int j = p + G::P * t;
-#pragma unroll
-            for (int r = 0; r < RF; ++r) w[r] = buf[pad(j + r * (G::L / RF))];
-#pragma unroll
-            for (int r = 1; r < RF; ++r) w[r] = cmul(w[r], tw.fin(t, r));
-            dftR<T, RF>(w);
-            // output index j + r * (L/RF) = p + P (t + r * NT)
-#pragma unroll
-            for (int r = 0; r < RF; ++r) v[t + r * NT] = w[r];
-        }
-    }
-}
+using namespace dev;
 
 // Blocks that share an XCD get neighbouring lines, so that the strided passes
 // reuse cache lines within one L2.
@@ -324,244 +43,24 @@ __device__ __forceinline__ unsigned block_line(unsigned lpb)
     return lb * lpb;
 }
 
-// Rank split: a block holds S waves that share the same lines; wave s takes
-// the terms l = s, s + S, ... and the S partial sums are added in LDS at the
-// end (fixed order, so results do not depend on timing).  Every wave runs the
-// same number of iterations (ceil(rank / S)) so that all of them meet every
-// block barrier; a wave whose term index runs past the rank computes a term
-// it then discards.
+// The one-pass kernel: a block holds S split groups that share the same
+// lines (rank split, only for lines held by a single wave).
 template <class T, int LOG2L, int FWD>
 __global__ void __launch_bounds__(Geo<LOG2L>::BLOCK == 64 ? 256 : Geo<LOG2L>::BLOCK) axis_pass(AxisLaunch a)
 {
     using G = Geo<LOG2L>;
     extern __shared__ unsigned char lds_raw[];
     cpx<T> *smem = reinterpret_cast<cpx<T> *>(lds_raw);
-    // lanes of one split group: G::BLOCK threads (one wave for L <= 1024)
     const int S = (int)(blockDim.x / G::BLOCK);
-    const int sgrp = (int)threadIdx.x / G::BLOCK;
-    const int tid = (int)threadIdx.x % G::BLOCK;
-    const int slot = tid / G::P;
-    const int p = tid % G::P;
-    cpx<T> *buf = smem + (sgrp * G::LPB + slot) * G::BUF;
-    T *sbuf = reinterpret_cast<T *>(buf);
-
-    // the host guarantees lines * n < 2^31, so 32-bit indexing is exact
-    const unsigned line = block_line(G::LPB) + (unsigned)slot;
-    const bool active = line < (unsigned)a.lines;
-    const unsigned stride = (unsigned)a.stride;
-    const unsigned outer = active ? line / stride : 0u;
-    const unsigned inner = active ? line - outer * stride : 0u;
-    const unsigned base = outer * (unsigned)a.n * stride + inner;
-    const int n = a.n, nu0 = a.nu0, rank = a.rank;
-
     const cpx<T> *tw = reinterpret_cast<const cpx<T> *>(a.tw);
-    const cpx<T> *uf = reinterpret_cast<const cpx<T> *>(a.u);
-    const cpx<T> *vf = reinterpret_cast<const cpx<T> *>(a.v);
-    const T *wv = reinterpret_cast<const T *>(a.wv);
-    const T *wvt = reinterpret_cast<const T *>(a.wvt);
-
-    Twiddles<T, LOG2L> twd;
     if constexpr (tw_mode<T, LOG2L>() == 1) {
         cpx<T> *tws = smem + S * G::LPB * G::BUF;
         for (int i = (int)threadIdx.x; i < G::L; i += (int)blockDim.x) tws[i] = tw[i];
         __syncthreads();
-        twd.load(tws, p);
-    } else {
-        twd.load(tw, p);
+        tw = tws;
     }
-
-    // the line, in the lane-owned layout (zero beyond n); dtype branch is uniform
-    T x[16];
-    if (a.in_f64) {
-        const double *src = reinterpret_cast<const double *>(a.in);
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int k = p + G::P * q;
-            x[q] = (active && k < n) ? (T)src[base + (unsigned)k * stride] : (T)0;
-        }
-    } else {
-        const float *src = reinterpret_cast<const float *>(a.in);
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int k = p + G::P * q;
-            x[q] = (active && k < n) ? (T)src[base + (unsigned)k * stride] : (T)0;
-        }
-    }
-    double acc[16];
-    const int iters = (rank + S - 1) / S;
-#ifndef JT_FULL_FAST
-#define JT_FULL_FAST 1
-#endif
-    const bool full = JT_FULL_FAST && (n == G::L);  // uniform: the line fills every owned slot
-
-    if constexpr (FWD) {
-        // ---- direct block (split group 0): out_j = sum_{k<nu0} WV[k][j] alpha_k
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int k = p + G::P * q;
-            if (k < nu0) sbuf[k] = x[q];
-        }
-        sync_line<G::P>();
-        if (full) {
-            // all 16 outputs exist: one batch of 16 loads per degree k
-            T s[16];
-#pragma unroll
-            for (int q = 0; q < 16; ++q) s[q] = 0;
-            const int kmax = (sgrp == 0) ? nu0 : 0;
-            for (int k = 0; k < kmax; ++k) {
-                const T ak = sbuf[k];
-#pragma unroll
-                for (int q = 0; q < 16; ++q) s[q] += wv[k * n + p + G::P * q] * ak;
-            }
-#pragma unroll
-            for (int q = 0; q < 16; ++q) acc[q] = (double)s[q];
-        } else {
-#pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int j = p + G::P * q;
-                T s = 0;
-                if (sgrp == 0 && j < n)
-                    for (int k = 0; k < nu0; ++k) s += wv[k * n + j] * sbuf[k];
-                acc[q] = (double)s;
-            }
-        }
-        for (int it = 0; it < iters; ++it) {
-            const int l0 = it * S + sgrp;
-            const bool keep = l0 < rank;
-            const int l = keep ? l0 : rank - 1;
-            cpx<T> v[16];
-#pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const cpx<T> f = vf[l * G::L + p + G::P * q];
-                v[q] = {f.x * x[q], f.y * x[q]};
-            }
-            sync_line<G::P>();  // previous users of buf are done
-            fft_line<T, LOG2L>(v, buf, p, twd);
-            sync_line<G::P>();
-#pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int m = p + G::P * q;
-                if (m <= G::L / 2) buf[pad(m)] = v[q];
-            }
-            sync_line<G::P>();
-            if (keep) {
-                const cpx<T> *ul = uf + l * n;
-                if (full) {
-                    // every owned node exists: no per-element guards, loads batch
-#pragma unroll
-                    for (int q = 0; q < 16; ++q) {
-                        const int j = p + G::P * q;
-                        const cpx<T> y = buf[pad(a.bins[j])];
-                        const cpx<T> u = ul[j];
-                        acc[q] += (double)(u.x * y.x - u.y * y.y);
-                    }
-                } else {
-#pragma unroll
-                    for (int q = 0; q < 16; ++q) {
-                        const int j = p + G::P * q;
-                        if (j < n) {
-                            const cpx<T> y = buf[pad(a.bins[j])];
-                            const cpx<T> u = ul[j];
-                            acc[q] += (double)(u.x * y.x - u.y * y.y);
-                        }
-                    }
-                }
-            }
-        }
-    } else {
-        // ---- direct block (split group 0): alpha_k = sum_j WV[k][j] g_j for k < nu0
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int j = p + G::P * q;
-            if (j < n) sbuf[j] = x[q];
-        }
-        sync_line<G::P>();
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int k = p + G::P * q;
-            T s = 0;
-            if (sgrp == 0 && k < nu0)
-                for (int j = 0; j < n; ++j) s += wvt[j * nu0 + k] * sbuf[j];
-            acc[q] = (double)s;
-        }
-        for (int it = 0; it < iters; ++it) {
-            const int l0 = it * S + sgrp;
-            const bool keep = l0 < rank;
-            const int l = keep ? l0 : rank - 1;
-            sync_line<G::P>();  // previous users of buf are done
-            if (full) {
-#pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    const int j = p + G::P * q;
-                    const cpx<T> u = uf[l * n + j];
-                    buf[pad(j)] = {u.x * x[q], u.y * x[q]};
-                }
-            } else {
-#pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    const int j = p + G::P * q;
-                    if (j < n) {
-                        const cpx<T> u = uf[l * n + j];
-                        buf[pad(j)] = {u.x * x[q], u.y * x[q]};
-                    }
-                }
-            }
-            sync_line<G::P>();
-            cpx<T> v[16];
-#pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int m = p + G::P * q;
-                cpx<T> z = {(T)0, (T)0};
-                if (m <= G::L / 2) {
-                    const int j0 = a.binptr[m], j1 = a.binptr[m + 1];
-                    for (int jj = j0; jj < j1; ++jj) z = z + buf[pad(jj)];
-                }
-                v[q] = z;
-            }
-            sync_line<G::P>();
-            fft_line<T, LOG2L>(v, buf, p, twd);
-            if (keep) {
-#pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    const int k = p + G::P * q;
-                    const cpx<T> f = vf[l * G::L + k];
-                    acc[q] += (double)(f.x * v[q].x - f.y * v[q].y);
-                }
-            }
-        }
-    }
-    // ---- sum the S partial results in LDS (fixed order), then store.
-    // All reads of the input happened before the first barrier, so the output
-    // may alias the input (in-place passes).
-    double *part = reinterpret_cast<double *>(buf);  // L doubles fit in one line buffer
-    if (S > 1) {
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < 16; ++q) part[p + G::P * q] = acc[q];
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            double t = 0.0;
-            for (int s2 = 0; s2 < S; ++s2)
-                t += reinterpret_cast<const double *>(smem + (s2 * G::LPB + slot) * G::BUF)[p + G::P * q];
-            acc[q] = t;
-        }
-    }
-    if (a.out_f64) {
-        double *dst = reinterpret_cast<double *>(a.out);
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int i = p + G::P * q;
-            if (active && i < n && (q % S) == sgrp) dst[base + (unsigned)i * stride] = acc[q];
-        }
-    } else {
-        float *dst = reinterpret_cast<float *>(a.out);
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int i = p + G::P * q;
-            if (active && i < n && (q % S) == sgrp) dst[base + (unsigned)i * stride] = (float)acc[q];
-        }
-    }
+    pass_lines<T, LOG2L, FWD>(a, block_line(G::LPB), (unsigned)a.lines, S, (int)threadIdx.x / G::BLOCK,
+                              (int)threadIdx.x % G::BLOCK, smem, tw);
 }
 
 template <class T, int LOG2L>

@@ -1,0 +1,162 @@
+// Persistent batch kernel: one launch runs every axis pass of every item of
+// a batch of independent transforms (uneven n, d and (a, b)), pulling work
+// units from a device queue.  Each unit runs the same fused per-line body as
+// the one-pass kernel (eqs. (50) and (51)).
+//
+// Block shape: 512 threads (8 waves).  For a unit of FFT length L the block
+// is cut into groups of Geo<L>::BLOCK threads (one wave, or P = L/16 lanes
+// for longer lines; a 16384-point line puts two lanes on each of the 512
+// threads); S consecutive groups share one set of LPB lines (rank split), so
+// a unit holds (groups / S) * LPB lines.
+#include <hip/hip_runtime.h>
+
+#include "batch.h"
+#include "fft_line.h"
+
+namespace jt {
+namespace {
+
+using namespace dev;
+
+// Bounded wait for a pass to complete (about 4 s at most): on timeout the
+// error word gets kBatchErrWaitTimeout and the unit proceeds, so the grid
+// always drains.
+__device__ void wait_done(const uint32_t *ctr, uint32_t need, uint32_t *err)
+{
+    for (uint32_t spins = 0;; ++spins) {
+        const uint32_t v = __hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        if (v >= need) return;
+        if (spins > (1u << 23)) {
+            atomicOr(err, kBatchErrWaitTimeout);
+            return;
+        }
+        __builtin_amdgcn_s_sleep(8);
+    }
+}
+
+// One variant per length, kept out of line: inlined together, the nine
+// variants of both directions would share one register allocation and spill.
+template <class T, int LOG2L>
+__device__ __attribute__((noinline)) void run_unit(const PassDesc &d, const WorkUnit &w, const BatchLaunch &b, cpx<T> *smem)
+{
+    constexpr int NT = kBatchThreads;
+    constexpr int VL = ((1 << LOG2L) / 16 > NT) ? ((1 << LOG2L) / 16) / NT : 1;
+    using G = Geo<LOG2L, VL>;
+    if constexpr (sizeof(T) == 8 && LOG2L > 13) {
+        return;  // rejected on the host (the line buffer would not fit in LDS)
+    } else {
+        AxisLaunch a;
+        a.in = (d.in_from_out ? (const unsigned char *)b.out_base : b.in_base) + d.in_off;
+        a.out = b.out_base + d.out_off;
+        a.in_f64 = d.in_f64;
+        a.out_f64 = d.out_f64;
+        a.lines = d.lines;
+        a.stride = d.stride;
+        a.n = d.n;
+        a.L = d.L;
+        a.nu0 = d.nu0;
+        a.rank = d.rank;
+        a.max_per_bin = d.max_per_bin;
+        a.forward = d.forward;
+        a.fp32 = sizeof(T) == 4;
+        a.tw = d.tw;
+        a.bins = d.bins;
+        a.binptr = d.binptr;
+        a.wv = d.wv;
+        a.wvt = d.wvt;
+        a.u = d.u;
+        a.v = d.v;
+        const int S = w.split;
+        const int grp = (int)threadIdx.x / G::BLOCK;
+        const int vb = grp / S, sgrp = grp % S;
+        const unsigned line0 = (unsigned)w.line0 + (unsigned)(vb * G::LPB);
+        const unsigned line_end = (unsigned)(w.line0 + w.nlines);
+        cpx<T> *vs = smem + vb * S * G::LPB * G::BUF;
+        const cpx<T> *tw = reinterpret_cast<const cpx<T> *>(d.tw);
+        if (d.forward)
+            pass_lines<T, LOG2L, 1, VL>(a, line0, line_end, S, sgrp, (int)threadIdx.x % G::BLOCK, vs, tw);
+        else
+            pass_lines<T, LOG2L, 0, VL>(a, line0, line_end, S, sgrp, (int)threadIdx.x % G::BLOCK, vs, tw);
+    }
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBatchThreads) batch_kernel(BatchLaunch b)
+{
+    extern __shared__ unsigned char lds_raw[];
+    cpx<T> *smem = reinterpret_cast<cpx<T> *>(lds_raw);
+    __shared__ int s_unit;
+    uint32_t *head = b.counters;
+    uint32_t *err = b.counters + 1;
+    uint32_t *done = b.counters + 2;
+    for (;;) {
+        if (threadIdx.x == 0) s_unit = (int)atomicAdd(head, 1u);
+        __syncthreads();
+        const int u = s_unit;
+        __syncthreads();  // every thread has read s_unit before it is overwritten
+        if (u >= b.nunits) break;
+        const WorkUnit w = b.units[u];
+        const PassDesc d = b.passes[w.pass];
+        if (w.wait_pass >= 0) {
+            if (threadIdx.x == 0) wait_done(done + w.wait_pass, (uint32_t)w.wait_count, err);
+            __syncthreads();
+            // the previous pass's results were written by other blocks (other XCDs)
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        switch (d.L) {
+        case 64: run_unit<T, 6>(d, w, b, smem); break;
+        case 128: run_unit<T, 7>(d, w, b, smem); break;
+        case 256: run_unit<T, 8>(d, w, b, smem); break;
+        case 512: run_unit<T, 9>(d, w, b, smem); break;
+        case 1024: run_unit<T, 10>(d, w, b, smem); break;
+        case 2048: run_unit<T, 11>(d, w, b, smem); break;
+        case 4096: run_unit<T, 12>(d, w, b, smem); break;
+        case 8192: run_unit<T, 13>(d, w, b, smem); break;
+        case 16384: run_unit<T, 14>(d, w, b, smem); break;
+        default:
+            if (threadIdx.x == 0) atomicOr(err, kBatchErrBadLength);
+            break;
+        }
+        // publish this unit's stores device-wide, then count it done
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (threadIdx.x == 0)
+            __hip_atomic_fetch_add(done + w.pass, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Counters are cleared by a kernel (not a memset node), so that a captured
+// graph of a run replays correctly.
+__global__ void __launch_bounds__(256) clear_words(uint32_t *w, int count)
+{
+    for (int i = (int)threadIdx.x; i < count; i += (int)blockDim.x) w[i] = 0u;
+}
+
+template <class T>
+hipError_t launch_t(const BatchLaunch &b, hipStream_t s)
+{
+    constexpr bool f32 = sizeof(T) == 4;
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&batch_kernel<T>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)batch_lds_bytes(f32));
+        (void)hipGetLastError();
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(batch_kernel<T>, dim3((unsigned)b.grid), dim3(kBatchThreads), batch_lds_bytes(f32), s, b);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_batch(const BatchLaunch &b, hipStream_t stream)
+{
+    if (b.nunits <= 0) return hipSuccess;
+    if (b.grid <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(clear_words, dim3(1), dim3(256), 0, stream, b.counters, 2 + b.npasses);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return b.fp32 ? launch_t<float>(b, stream) : launch_t<double>(b, stream);
+}
+
+}  // namespace jt

@@ -1,4 +1,5 @@
 #include "dense.h"
+#include "threads.h"
 
 #include <algorithm>
 #include <cmath>
@@ -42,11 +43,14 @@ std::vector<int> pivoted_qr(const CMat &m_in, int steps, CMat *q_out)
         // pick the column of largest remaining norm (recomputed, no downdating)
         int best = k;
         double bestn = -1.0;
-        for (int j = k; j < nc; ++j) {
+        std::vector<double> cn(nc - k);
+        parallel_for(nc - k, [&](int jj) {
             double s = 0.0;
-            for (int i = k; i < nr; ++i) s += std::norm(r(i, j));
-            if (s > bestn) { bestn = s; best = j; }
-        }
+            for (int i = k; i < nr; ++i) s += std::norm(r(i, k + jj));
+            cn[jj] = s;
+        });
+        for (int j = k; j < nc; ++j)
+            if (cn[j - k] > bestn) { bestn = cn[j - k]; best = j; }
         if (best != k) {
             for (int i = 0; i < nr; ++i) std::swap(r(i, k), r(i, best));
             std::swap(perm[k], perm[best]);
@@ -66,12 +70,13 @@ std::vector<int> pivoted_qr(const CMat &m_in, int steps, CMat *q_out)
         double vv = 0.0;
         for (int i = k; i < nr; ++i) vv += std::norm(v[i]);
         double beta = (vv > 0.0) ? 2.0 / vv : 0.0;
-        for (int j = k; j < nc; ++j) {
+        parallel_for(nc - k, [&](int jj) {
+            const int j = k + jj;
             cd dot(0.0, 0.0);
             for (int i = k; i < nr; ++i) dot += std::conj(v[i]) * r(i, j);
             dot *= beta;
             for (int i = k; i < nr; ++i) r(i, j) -= v[i] * dot;
-        }
+        });
         refl.push_back(v);
         refl_beta.push_back(beta);
     }

@@ -1,0 +1,651 @@
+// Device building blocks of the axis pass, shared by the one-pass kernel and
+// the persistent batch kernel: radix-16 Stockham FFT of a line held in
+// registers (lane-owned layout) and the fused scale -> FFT -> gather ->
+// accumulate body of eqs. (50) and (51).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "launch.h"
+
+namespace jt {
+namespace dev {
+
+
+template <class T>
+struct cpx {
+    T x, y;
+};
+
+template <class T>
+__device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <class T>
+__device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <class T>
+__device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b)
+{
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <class T>
+__device__ __forceinline__ cpx<T> muli(cpx<T> a) { return {-a.y, a.x}; }
+
+// exp(2 pi i e / 16) for e = 0..15
+constexpr double kW16c[16] = {
+    1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+    0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+    -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173,
+    0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613};
+constexpr double kW16s[16] = {
+    0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613,
+    1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+    0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+    -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173};
+
+template <class T, int E>
+__device__ __forceinline__ cpx<T> w16(cpx<T> a)
+{
+    constexpr int e = E & 15;
+    if constexpr (e == 0) {
+        return a;
+    } else if constexpr (e == 4) {
+        return {-a.y, a.x};
+    } else if constexpr (e == 8) {
+        return {-a.x, -a.y};
+    } else if constexpr (e == 12) {
+        return {a.y, -a.x};
+    } else if constexpr (e == 2 || e == 6 || e == 10 || e == 14) {
+        // (c, s) with |c| = |s| = sqrt(2)/2
+        constexpr T r = (T)0.70710678118654752440;
+        constexpr T cs = (e == 2 || e == 14) ? r : -r;
+        constexpr T sn = (e == 2 || e == 6) ? r : -r;
+        return {cs * a.x - sn * a.y, sn * a.x + cs * a.y};
+    } else {
+        constexpr T c = (T)kW16c[e], s = (T)kW16s[e];
+        return {c * a.x - s * a.y, s * a.x + c * a.y};
+    }
+}
+
+template <class T>
+__device__ __forceinline__ void dft2(cpx<T> &a0, cpx<T> &a1)
+{
+    cpx<T> t = a0;
+    a0 = t + a1;
+    a1 = t - a1;
+}
+
+// sign +:  X_m = sum_k a_k i^{k m}
+template <class T>
+__device__ __forceinline__ void dft4(cpx<T> &a0, cpx<T> &a1, cpx<T> &a2, cpx<T> &a3)
+{
+    cpx<T> t0 = a0 + a2, t1 = a0 - a2, t2 = a1 + a3, t3 = muli(a1 - a3);
+    a0 = t0 + t2;
+    a2 = t0 - t2;
+    a1 = t1 + t3;
+    a3 = t1 - t3;
+}
+
+// In-place 8-point DFT (sign +), natural order in and out: 8 = 2 x 4.
+template <class T>
+__device__ __forceinline__ void dft8(cpx<T> *v)
+{
+    // k = k1 + 2 k2:  4-point DFTs over k2 for k1 = 0, 1
+    dft4(v[0], v[2], v[4], v[6]);
+    dft4(v[1], v[3], v[5], v[7]);
+    // twiddle omega_8^{k1 m2} = omega_16^{2 k1 m2}
+    v[3] = w16<T, 2>(v[3]);
+    v[5] = w16<T, 4>(v[5]);
+    v[7] = w16<T, 6>(v[7]);
+    // X[m2 + 4 m1] = 2-point DFT over k1 of Y[k1][m2] (stored at v[k1 + 2 m2])
+    cpx<T> o[8];
+#pragma unroll
+    for (int m2 = 0; m2 < 4; ++m2) {
+        cpx<T> a = v[2 * m2], b = v[2 * m2 + 1];
+        o[m2] = a + b;
+        o[m2 + 4] = a - b;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = o[i];
+}
+
+// In-place 16-point DFT (sign +), natural order in and out: 16 = 4 x 4.
+template <class T>
+__device__ __forceinline__ void dft16(cpx<T> *v)
+{
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) dft4(v[k1], v[k1 + 4], v[k1 + 8], v[k1 + 12]);
+    v[5] = w16<T, 1>(v[5]);
+    v[9] = w16<T, 2>(v[9]);
+    v[13] = w16<T, 3>(v[13]);
+    v[6] = w16<T, 2>(v[6]);
+    v[10] = w16<T, 4>(v[10]);
+    v[14] = w16<T, 6>(v[14]);
+    v[7] = w16<T, 3>(v[7]);
+    v[11] = w16<T, 6>(v[11]);
+    v[15] = w16<T, 9>(v[15]);
+    cpx<T> o[16];
+#pragma unroll
+    for (int m2 = 0; m2 < 4; ++m2) {
+        cpx<T> a0 = v[4 * m2], a1 = v[4 * m2 + 1], a2 = v[4 * m2 + 2], a3 = v[4 * m2 + 3];
+        dft4(a0, a1, a2, a3);
+        o[m2] = a0;
+        o[m2 + 4] = a1;
+        o[m2 + 8] = a2;
+        o[m2 + 12] = a3;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = o[i];
+}
+
+template <class T, int R>
+__device__ __forceinline__ void dftR(cpx<T> *v)
+{
+    if constexpr (R == 2) dft2(v[0], v[1]);
+    else if constexpr (R == 4) dft4(v[0], v[1], v[2], v[3]);
+    else if constexpr (R == 8) dft8(v);
+    else dft16(v);
+}
+
+// Synchronisation of the lanes that share one line buffer.  A line of up to
+// 1024 points lives in one wave: its lanes exchange data through LDS in
+// program order, so a wave-scope fence (no instruction, it only stops the
+// compiler from moving LDS accesses across it) is enough, and the other waves
+// of the block keep running.  Longer lines span several waves and need the
+// block barrier.
+template <int TPL>
+__device__ __forceinline__ void sync_line()
+{
+    if constexpr (TPL <= 64) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
+// padded LDS index: one spare slot every 16 elements
+__device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
+
+// Sum v[0..K-1] over the TPL threads of one line; every thread of the line
+// gets the totals.  Inside a wave: butterfly over lanes (the line's lanes
+// form an aligned segment of TPL lanes).  A line over several waves adds the
+// per-wave totals through red (K doubles per wave, in LDS) in wave order.
+// Every thread of the line must call it.
+template <int TPL, int K>
+__device__ __forceinline__ void line_sum(double *v, double *red, int t)
+{
+    constexpr int W = TPL < 64 ? TPL : 64;
+#pragma unroll
+    for (int off = W / 2; off >= 1; off /= 2)
+#pragma unroll
+        for (int c = 0; c < K; ++c) v[c] += __shfl_xor(v[c], off, W);
+    if constexpr (TPL > 64) {
+        constexpr int NW = TPL / 64;
+        const int w = t / 64;
+        __syncthreads();  // previous readers of red are done
+        if ((t & 63) == 0)
+#pragma unroll
+            for (int c = 0; c < K; ++c) red[w * K + c] = v[c];
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            double s = 0.0;
+#pragma unroll
+            for (int i = 0; i < NW; ++i) s += red[i * K + c];
+            v[c] = s;
+        }
+    }
+}
+
+// Shape of one line of length L = 2^LOG2L: P = L/16 lanes, each holding 16
+// elements.  A thread carries VL lanes (p and p + TPL, ...), so a line takes
+// TPL = P / VL threads; lines shorter than a wave share one (LPB lines per
+// group of BLOCK threads).
+template <int LOG2L, int VL = 1>
+struct Geo {
+    static constexpr int L = 1 << LOG2L;
+    static constexpr int P = L / 16;                     // lanes per line
+    static constexpr int TPL = P / VL;                   // threads per line
+    static constexpr int S16 = LOG2L / 4;                // radix-16 passes
+    static constexpr int F = LOG2L % 4;
+    static constexpr int RF = 1 << F;                    // final radix (1: none)
+    static constexpr int NMID = S16 - 1;                 // radix-16 passes after the first
+    static constexpr int BLOCK = (TPL < 64) ? 64 : TPL;  // threads per group
+    static constexpr int LPB = BLOCK / TPL;              // lines per group
+    static constexpr int BUF = L + L / 16;               // padded line buffer (complex)
+    static_assert(VL == 1 || TPL >= 64, "several lanes per thread only for lines spanning whole waves");
+};
+
+// Twiddles of all passes after the first.  They depend only on the lane, so
+// the fp32 kernels keep them in registers for the whole kernel; the fp64
+// kernels (twice the register cost) and blocks of 512+ threads read them from
+// the L-entry table when a pass needs them.
+// Where the per-pass twiddles live: 0 = registers (loaded once), 1 = a copy
+// of the table in LDS (loaded once per block), 2 = the table in global memory
+// (L1/L2 resident).  Measured on the 1024-point lines, 2 is fastest in both
+// precisions: registers are better spent on occupancy.
+#ifndef JT_TW_MODE_F32
+#define JT_TW_MODE_F32 2
+#endif
+#ifndef JT_TW_MODE_F64
+#define JT_TW_MODE_F64 2
+#endif
+template <class T, int LOG2L>
+constexpr int tw_mode()
+{
+    if constexpr (Geo<LOG2L>::BLOCK > 256) return 2;  // big lines: too few registers per lane
+    else return sizeof(T) == 4 ? JT_TW_MODE_F32 : JT_TW_MODE_F64;
+}
+
+template <class T, int LOG2L>
+struct Twiddles {
+    using G = Geo<LOG2L>;
+    static constexpr bool kHoist = tw_mode<T, LOG2L>() == 0;
+    cpx<T> mid_[(kHoist && G::NMID > 0) ? G::NMID : 1][15];
+    cpx<T> fin_[(kHoist && G::RF > 1) ? 16 / G::RF : 1][(G::RF > 1) ? G::RF - 1 : 1];
+    const cpx<T> *tw;
+    int p;
+
+    // pass i+1 has Ns = 16^(i+1); factor omega_{16 Ns}^{(p mod Ns) r} = tw[(p mod Ns) r L / (16 Ns)]
+    static __device__ __forceinline__ int mid_index(int i, int r, int p)
+    {
+        int ns = 16;
+        for (int k = 0; k < i; ++k) ns *= 16;
+        return (p & (ns - 1)) * r * (G::L / (16 * ns));
+    }
+    // final pass (radix RF, Ns = L/RF): task j = p + P t, factor omega_L^{j r}
+    static __device__ __forceinline__ int fin_index(int t, int r, int p) { return (p + G::P * t) * r; }
+
+    __device__ __forceinline__ void load(const cpx<T> *table, int lane)
+    {
+        tw = table;
+        p = lane;
+        if constexpr (kHoist) {
+#pragma unroll
+            for (int i = 0; i < G::NMID; ++i)
+#pragma unroll
+                for (int r = 1; r < 16; ++r) mid_[i][r - 1] = tw[mid_index(i, r, p)];
+            if constexpr (G::RF > 1) {
+#pragma unroll
+                for (int t = 0; t < 16 / G::RF; ++t)
+#pragma unroll
+                    for (int r = 1; r < G::RF; ++r) fin_[t][r - 1] = tw[fin_index(t, r, p)];
+            }
+        }
+    }
+    __device__ __forceinline__ cpx<T> mid(int i, int r) const
+    {
+        if constexpr (kHoist) return mid_[i][r - 1];
+        else return tw[mid_index(i, r, p)];
+    }
+    __device__ __forceinline__ cpx<T> fin(int t, int r) const
+    {
+        if constexpr (kHoist) return fin_[t][r - 1];
+        else return tw[fin_index(t, r, p)];
+    }
+};
+
+// L-point DFT (sign +) of the line held in v (lane-owned layout: lane p = pv[h]
+// holds v[h][q] = x[p + P q]); on return v[h][q] = X[p + P q].  buf is this
+// line's LDS buffer.  Every thread of the line must call it (it contains the
+// line's barriers); the VL lanes of a thread are processed between the same
+// barriers.
+template <class T, int LOG2L, int VL>
+__device__ __forceinline__ void fft_line(cpx<T> (*v)[16], cpx<T> *buf, const int *pv,
+                                         const Twiddles<T, LOG2L> *tw)
+{
+    using G = Geo<LOG2L, VL>;
+    static_assert(G::L >= 64, "lines shorter than 64 use the dense path with L = 64");
+    // pass 0: Ns = 1, no twiddles, inputs are already v[r] = x[p + r P]
+#pragma unroll
+    for (int h = 0; h < VL; ++h) {
+        dft16(v[h]);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) buf[pad(pv[h] * 16 + r)] = v[h][r];
+    }
+    int ns = 16;
+#pragma unroll
+    for (int i = 0; i < G::NMID; ++i) {
+        sync_line<G::TPL>();
+#pragma unroll
+        for (int h = 0; h < VL; ++h) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) v[h][r] = buf[pad(pv[h] + r * G::P)];
+#pragma unroll
+            for (int r = 1; r < 16; ++r) v[h][r] = cmul(v[h][r], tw[h].mid(i, r));
+            dft16(v[h]);
+        }
+        const bool last = (G::RF == 1) && (i == G::NMID - 1);
+        if (!last) {
+            sync_line<G::TPL>();
+#pragma unroll
+            for (int h = 0; h < VL; ++h) {
+                const int p = pv[h];
+                const int base = (p / ns) * ns * 16 + (p & (ns - 1));
+#pragma unroll
+                for (int r = 0; r < 16; ++r) buf[pad(base + r * ns)] = v[h][r];
+            }
+        }
+        ns *= 16;
+    }
+    if constexpr (G::RF > 1) {
+        constexpr int RF = G::RF, NT = 16 / RF;
+        sync_line<G::TPL>();
+#pragma unroll
+        for (int h = 0; h < VL; ++h) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                cpx<T> w[RF];
+                const int j = pv[h] + G::P * t;
+#pragma unroll
+                for (int r = 0; r < RF; ++r) w[r] = buf[pad(j + r * (G::L / RF))];
+#pragma unroll
+                for (int r = 1; r < RF; ++r) w[r] = cmul(w[r], tw[h].fin(t, r));
+                dftR<T, RF>(w);
+                // output index j + r * (L/RF) = p + P (t + r * NT)
+#pragma unroll
+                for (int r = 0; r < RF; ++r) v[h][t + r * NT] = w[r];
+            }
+        }
+    }
+}
+
+// Everything one split group does for its LPB lines.  The caller arranges
+// the threads: S split groups of G::BLOCK threads share lines line0 ..
+// line0 + LPB - 1 (lines at or past line_end are inactive); group sgrp takes
+// the terms l = sgrp, sgrp + S, ... and the S partial sums are added in LDS
+// at the end (fixed order, so results do not depend on timing).  Every group
+// runs the same number of iterations (ceil(rank / S)) so that all of them
+// meet every block barrier; a group whose term index runs past the rank
+// computes a term it then discards.  smem holds S * LPB line buffers for
+// these groups; tw is the L-entry twiddle table (global or LDS).  Every
+// thread of the block must call this with the same S and the same rank.
+// A thread carries VL lanes of its line (VL > 1 only when S == 1).
+template <class T, int LOG2L, int FWD, int VL = 1>
+__device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, unsigned line_end, int S, int sgrp,
+                                           int tid, cpx<T> *smem, const cpx<T> *tw)
+{
+    using G = Geo<LOG2L, VL>;
+    const int slot = tid / G::TPL;
+    int pv[VL];
+#pragma unroll
+    for (int h = 0; h < VL; ++h) pv[h] = tid % G::TPL + h * G::TPL;
+    cpx<T> *buf = smem + (sgrp * G::LPB + slot) * G::BUF;
+    T *sbuf = reinterpret_cast<T *>(buf);
+
+    // the host guarantees lines * n < 2^31, so 32-bit indexing is exact
+    const unsigned line = line0 + (unsigned)slot;
+    const bool active = line < line_end;
+    const unsigned stride = (unsigned)a.stride;
+    const unsigned outer = active ? line / stride : 0u;
+    const unsigned inner = active ? line - outer * stride : 0u;
+    const unsigned base = outer * (unsigned)a.n * stride + inner;
+    const int n = a.n, nu0 = a.nu0, rank = a.rank;
+
+    const cpx<T> *uf = reinterpret_cast<const cpx<T> *>(a.u);
+    const cpx<T> *vf = reinterpret_cast<const cpx<T> *>(a.v);
+    const T *wv = reinterpret_cast<const T *>(a.wv);
+    const T *wvt = reinterpret_cast<const T *>(a.wvt);
+
+    Twiddles<T, LOG2L> twd[VL];
+#pragma unroll
+    for (int h = 0; h < VL; ++h) twd[h].load(tw, pv[h]);
+
+    // the line, in the lane-owned layout (zero beyond n); dtype branch is uniform
+    T x[VL][16];
+    if (a.in_f64) {
+        const double *src = reinterpret_cast<const double *>(a.in);
+#pragma unroll
+        for (int h = 0; h < VL; ++h)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int k = pv[h] + G::P * q;
+                x[h][q] = (active && k < n) ? (T)src[base + (unsigned)k * stride] : (T)0;
+            }
+    } else {
+        const float *src = reinterpret_cast<const float *>(a.in);
+#pragma unroll
+        for (int h = 0; h < VL; ++h)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int k = pv[h] + G::P * q;
+                x[h][q] = (active && k < n) ? (T)src[base + (unsigned)k * stride] : (T)0;
+            }
+    }
+    double acc[VL][16];
+    const int iters = (rank + S - 1) / S;
+#ifndef JT_FULL_FAST
+#define JT_FULL_FAST 1
+#endif
+    const bool full = JT_FULL_FAST && (n == G::L);  // uniform: the line fills every owned slot
+
+    if constexpr (FWD) {
+        // ---- direct block (split group 0): out_j = sum_{k<nu0} WV[k][j] alpha_k
+#pragma unroll
+        for (int h = 0; h < VL; ++h)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int k = pv[h] + G::P * q;
+                if (k < nu0) sbuf[k] = x[h][q];
+            }
+        sync_line<G::TPL>();
+        if (full) {
+            // all 16 outputs exist: one batch of 16 loads per degree k
+            T s[VL][16];
+#pragma unroll
+            for (int h = 0; h < VL; ++h)
+#pragma unroll
+                for (int q = 0; q < 16; ++q) s[h][q] = 0;
+            const int kmax = (sgrp == 0) ? nu0 : 0;
+            for (int k = 0; k < kmax; ++k) {
+                const T ak = sbuf[k];
+#pragma unroll
+                for (int h = 0; h < VL; ++h)
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) s[h][q] += wv[k * n + pv[h] + G::P * q] * ak;
+            }
+#pragma unroll
+            for (int h = 0; h < VL; ++h)
+#pragma unroll
+                for (int q = 0; q < 16; ++q) acc[h][q] = (double)s[h][q];
+        } else {
+#pragma unroll
+            for (int h = 0; h < VL; ++h)
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int j = pv[h] + G::P * q;
+                    T s = 0;
+                    if (sgrp == 0 && j < n)
+                        for (int k = 0; k < nu0; ++k) s += wv[k * n + j] * sbuf[k];
+                    acc[h][q] = (double)s;
+                }
+        }
+        for (int it = 0; it < iters; ++it) {
+            const int l0 = it * S + sgrp;
+            const bool keep = l0 < rank;
+            const int l = keep ? l0 : rank - 1;
+            cpx<T> v[VL][16];
+#pragma unroll
+            for (int h = 0; h < VL; ++h)
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const cpx<T> f = vf[l * G::L + pv[h] + G::P * q];
+                    v[h][q] = {f.x * x[h][q], f.y * x[h][q]};
+                }
+            sync_line<G::TPL>();  // previous users of buf are done
+            fft_line<T, LOG2L, VL>(v, buf, pv, twd);
+            sync_line<G::TPL>();
+#pragma unroll
+            for (int h = 0; h < VL; ++h)
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int m = pv[h] + G::P * q;
+                    if (m <= G::L / 2) buf[pad(m)] = v[h][q];
+                }
+            sync_line<G::TPL>();
+            if (keep) {
+                const cpx<T> *ul = uf + l * n;
+                if (full) {
+                    // every owned node exists: no per-element guards, loads batch
+#pragma unroll
+                    for (int h = 0; h < VL; ++h)
+#pragma unroll
+                        for (int q = 0; q < 16; ++q) {
+                            const int j = pv[h] + G::P * q;
+                            const cpx<T> y = buf[pad(a.bins[j])];
+                            const cpx<T> u = ul[j];
+                            acc[h][q] += (double)(u.x * y.x - u.y * y.y);
+                        }
+                } else {
+#pragma unroll
+                    for (int h = 0; h < VL; ++h)
+#pragma unroll
+                        for (int q = 0; q < 16; ++q) {
+                            const int j = pv[h] + G::P * q;
+                            if (j < n) {
+                                const cpx<T> y = buf[pad(a.bins[j])];
+                                const cpx<T> u = ul[j];
+                                acc[h][q] += (double)(u.x * y.x - u.y * y.y);
+                            }
+                        }
+                }
+            }
+        }
+    } else {
+        // ---- direct block (split group 0): alpha_k = sum_j WV[k][j] g_j for
+        // k < nu0.  Every lane sums over its own nodes for a chunk of KC
+        // degrees (coalesced rows of WV), the partial sums are added across
+        // the line's lanes, and the lane that owns degree k keeps the total.
+#pragma unroll
+        for (int h = 0; h < VL; ++h)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[h][q] = 0.0;
+        constexpr int KC = 8;
+        double *red = reinterpret_cast<double *>(buf);  // free until the first term
+        for (int k0 = 0; k0 < nu0; k0 += KC) {
+            double part[KC];
+#pragma unroll
+            for (int c = 0; c < KC; ++c) part[c] = 0.0;
+            if (sgrp == 0) {
+#pragma unroll
+                for (int h = 0; h < VL; ++h)
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) {
+                        const int j = pv[h] + G::P * q;
+                        if (j < n) {
+                            const double g = (double)x[h][q];
+#pragma unroll
+                            for (int c = 0; c < KC; ++c)
+                                if (k0 + c < nu0) part[c] += (double)wv[(k0 + c) * n + j] * g;
+                        }
+                    }
+            }
+            line_sum<G::TPL, KC>(part, red, tid % G::TPL);
+#pragma unroll
+            for (int c = 0; c < KC; ++c) {
+                const int k = k0 + c;
+#pragma unroll
+                for (int h = 0; h < VL; ++h)
+#pragma unroll
+                    for (int q = 0; q < 16; ++q)
+                        if (k < nu0 && k == pv[h] + G::P * q) acc[h][q] = part[c];
+            }
+        }
+        for (int it = 0; it < iters; ++it) {
+            const int l0 = it * S + sgrp;
+            const bool keep = l0 < rank;
+            const int l = keep ? l0 : rank - 1;
+            sync_line<G::TPL>();  // previous users of buf are done
+            if (full) {
+#pragma unroll
+                for (int h = 0; h < VL; ++h)
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) {
+                        const int j = pv[h] + G::P * q;
+                        const cpx<T> u = uf[l * n + j];
+                        buf[pad(j)] = {u.x * x[h][q], u.y * x[h][q]};
+                    }
+            } else {
+#pragma unroll
+                for (int h = 0; h < VL; ++h)
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) {
+                        const int j = pv[h] + G::P * q;
+                        if (j < n) {
+                            const cpx<T> u = uf[l * n + j];
+                            buf[pad(j)] = {u.x * x[h][q], u.y * x[h][q]};
+                        }
+                    }
+            }
+            sync_line<G::TPL>();
+            cpx<T> v[VL][16];
+#pragma unroll
+            for (int h = 0; h < VL; ++h)
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int m = pv[h] + G::P * q;
+                    cpx<T> z = {(T)0, (T)0};
+                    if (m <= G::L / 2) {
+                        const int j0 = a.binptr[m], j1 = a.binptr[m + 1];
+                        for (int jj = j0; jj < j1; ++jj) z = z + buf[pad(jj)];
+                    }
+                    v[h][q] = z;
+                }
+            sync_line<G::TPL>();
+            fft_line<T, LOG2L, VL>(v, buf, pv, twd);
+            if (keep) {
+#pragma unroll
+                for (int h = 0; h < VL; ++h)
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) {
+                        const int k = pv[h] + G::P * q;
+                        const cpx<T> f = vf[l * G::L + k];
+                        acc[h][q] += (double)(f.x * v[h][q].x - f.y * v[h][q].y);
+                    }
+            }
+        }
+    }
+    // ---- sum the S partial results in LDS (fixed order), then store.
+    // All reads of the input happened before the first barrier, so the output
+    // may alias the input (in-place passes).
+    double *part = reinterpret_cast<double *>(buf);  // L doubles fit in one line buffer
+    if (S > 1) {
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < VL; ++h)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) part[pv[h] + G::P * q] = acc[h][q];
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < VL; ++h)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                double t = 0.0;
+                for (int s2 = 0; s2 < S; ++s2)
+                    t += reinterpret_cast<const double *>(smem + (s2 * G::LPB + slot) * G::BUF)[pv[h] + G::P * q];
+                acc[h][q] = t;
+            }
+    }
+    if (a.out_f64) {
+        double *dst = reinterpret_cast<double *>(a.out);
+#pragma unroll
+        for (int h = 0; h < VL; ++h)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int i = pv[h] + G::P * q;
+                if (active && i < n && (q % S) == sgrp) dst[base + (unsigned)i * stride] = acc[h][q];
+            }
+    } else {
+        float *dst = reinterpret_cast<float *>(a.out);
+#pragma unroll
+        for (int h = 0; h < VL; ++h)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int i = pv[h] + G::P * q;
+                if (active && i < n && (q % S) == sgrp) dst[base + (unsigned)i * stride] = (float)acc[h][q];
+            }
+    }
+}
+
+}  // namespace dev
+}  // namespace jt

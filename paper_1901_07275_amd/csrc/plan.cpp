@@ -1,6 +1,7 @@
 // Host plan: nodes, weights, bins, direct block, companion function and the
 // randomized low-rank factorization of W B_n (Section 2.1, Section 3.1).
 #include "plan.h"
+#include "threads.h"
 
 #include <algorithm>
 #include <atomic>
@@ -18,30 +19,6 @@ namespace jt {
 typedef long double ld;
 static const ld kPi = 3.141592653589793238462643383279502884L;
 
-// ------------------------------------------------------------------ threads
-template <class F>
-static void parallel_for(int count, F f)
-{
-    unsigned hw = std::thread::hardware_concurrency();
-    int nt = (int)std::min<unsigned>(hw ? hw : 1, 16);
-    if (count < 64 || nt <= 1) {
-        for (int i = 0; i < count; ++i) f(i);
-        return;
-    }
-    std::atomic<int> next(0);
-    auto work = [&]() {
-        for (;;) {
-            int i0 = next.fetch_add(16);
-            if (i0 >= count) break;
-            int i1 = std::min(count, i0 + 16);
-            for (int i = i0; i < i1; ++i) f(i);
-        }
-    };
-    std::vector<std::thread> th;
-    for (int k = 1; k < nt; ++k) th.emplace_back(work);
-    work();
-    for (auto &t : th) t.join();
-}
 
 // ------------------------------------------------------------------ RNG
 // splitmix64: counter-based, so plans are reproducible for a given key.
@@ -103,7 +80,8 @@ static std::vector<int> merged(const std::vector<int> &x, const std::vector<int>
 // Orthonormal Jacobi polynomials for w(x) = (1-x)^a (1+x)^b:
 //   x p_k = be[k+1] p_{k+1} + al[k] p_k + be[k] p_{k-1},  p_0 = mu0^{-1/2}.
 struct Rec {
-    std::vector<ld> al, be;
+    std::vector<ld> al, be, ibe;        // ibe[k] = 1 / be[k] (k >= 1)
+    std::vector<double> al_d, be_d, ibe_d;  // the same, rounded to double
     ld mu0 = 0, sqrt_mu0 = 0;
 };
 
@@ -130,6 +108,11 @@ static Rec recurrence(int N, ld a, ld b)
             r.be[k] = sqrtl(4 * (ld)k * (k + a) * (k + b) * (k + ab) / (s * s * (s + 1) * (s - 1)));
         }
     }
+    r.ibe.assign(N + 2, 0);
+    for (int k = 1; k <= N + 1; ++k) r.ibe[k] = 1 / r.be[k];
+    r.al_d.assign(r.al.begin(), r.al.end());
+    r.be_d.assign(r.be.begin(), r.be.end());
+    r.ibe_d.assign(r.ibe.begin(), r.ibe.end());
     r.mu0 = expl((ab + 1) * logl(2.0L) + lgammal(a + 1) + lgammal(b + 1) - lgammal(ab + 2));
     r.sqrt_mu0 = sqrtl(r.mu0);
     return r;
@@ -140,7 +123,7 @@ static void eval_top(const Rec &r, int n, ld x, ld &pn, ld &pn1, ld &dpn, ld *dp
 {
     ld pm = 0, p = 1 / r.sqrt_mu0, dm = 0, d = 0;
     for (int k = 0; k < n; ++k) {
-        ld ip = 1 / r.be[k + 1];
+        ld ip = r.ibe[k + 1];
         ld pnew = ((x - r.al[k]) * p - r.be[k] * pm) * ip;
         ld dnew = ((x - r.al[k]) * d + p - r.be[k] * dm) * ip;
         pm = p; p = pnew;
@@ -166,8 +149,86 @@ static ld weight_at(const Rec &r, int n, ld x)
 // Newton iteration in t on p_n(cos t) from the interior asymptotic zeros
 // t_j ~ (j + a/2 - 1/4) pi / (n + (a+b+1)/2); a sign-change scan is the
 // fallback when the Newton roots are not n distinct increasing values.
-static bool newton_root(const Rec &r, int n, ld &t, ld lo, ld hi)
+// Double-precision Newton phase for up to 8 roots at once: the recurrence is
+// a chain of dependent multiply-adds, so walking 8 independent chains side by
+// side keeps the floating-point pipeline busy.  A lane stops when its step
+// drops below 1e-11 (conv = 1) or leaves its bracket (conv = 0).
+static void newton_double_group(const Rec &r, int n, int cnt, double *t, const double *lo,
+                                const double *hi, bool *conv)
 {
+    constexpr int G = 8;
+    bool act[G];
+    double x[G];
+    for (int i = 0; i < G; ++i) {
+        act[i] = i < cnt;
+        conv[i] = false;
+    }
+    const double p0 = (double)(1 / r.sqrt_mu0);
+    for (int it = 0; it < 40; ++it) {
+        bool any = false;
+        for (int i = 0; i < G; ++i) {
+            any |= act[i];
+            x[i] = (i < cnt) ? std::cos(t[i]) : 0.0;
+        }
+        if (!any) break;
+        double pm[G], p[G], dm[G], d[G];
+        for (int i = 0; i < G; ++i) { pm[i] = 0; p[i] = p0; dm[i] = 0; d[i] = 0; }
+        for (int k = 0; k < n; ++k) {
+            const double ip = r.ibe_d[k + 1], al = r.al_d[k], bk = r.be_d[k];
+            for (int i = 0; i < G; ++i) {
+                const double xa = x[i] - al;
+                const double pn = (xa * p[i] - bk * pm[i]) * ip;
+                const double dn = (xa * d[i] + p[i] - bk * dm[i]) * ip;
+                pm[i] = p[i]; p[i] = pn;
+                dm[i] = d[i]; d[i] = dn;
+            }
+        }
+        for (int i = 0; i < cnt; ++i) {
+            if (!act[i]) continue;
+            const double fp = -std::sin(t[i]) * d[i];
+            if (fp == 0 || !std::isfinite(fp) || !std::isfinite(p[i])) { act[i] = false; continue; }
+            const double step = p[i] / fp, tn = t[i] - step;
+            if (!(tn > lo[i] && tn < hi[i])) { act[i] = false; continue; }
+            t[i] = tn;
+            if (std::fabs(step) < 1e-11) { act[i] = false; conv[i] = true; }
+        }
+    }
+}
+
+// One long double Newton step from a root already accurate to double
+// precision, returning the Gauss-Jacobi weight as well.  The weight is the
+// reciprocal of F(x) = sum_{k<n} p_k(x)^2 = be_n (p_n' p_{n-1} - p_{n-1}' p_n)
+// (Christoffel-Darboux), evaluated at the starting point and carried to the
+// refined root to first order with F'/F = p_n'' / p_n' + O(p_n), where p_n''
+// comes from the Jacobi differential equation
+//   (1 - x^2) p'' + (b - a - (a + b + 2) x) p' + n (n + a + b + 1) p = 0.
+// One walk of the recurrence gives both the step and the weight; the
+// neglected terms are below 1e-20 relative for a starting error near 1e-16.
+static bool newton_final(const Rec &r, int n, ld a, ld b, ld &t, ld &omega)
+{
+    const ld x = cosl(t);
+    ld pn, pn1, dpn, dpn1;
+    eval_top(r, n, x, pn, pn1, dpn, &dpn1);
+    const ld fp = -sinl(t) * dpn;
+    if (fp == 0 || !std::isfinite((double)fp)) return false;
+    const ld step = pn / fp;
+    const ld tn = t - step;
+    // x(tn) - x(t) without cancellation
+    const ld dx = -2 * sinl((tn + t) / 2) * sinl((tn - t) / 2);
+    const ld omx2 = sinl(t) * sinl(t);  // 1 - x^2
+    const ld d2 = -((b - a - (a + b + 2) * x) * dpn + n * (n + a + b + 1) * pn) / omx2;
+    const ld F = r.be[n] * (dpn * pn1 - dpn1 * pn);
+    const ld Fn = F * (1 + dx * d2 / dpn);
+    if (!(Fn > 0)) return false;
+    t = tn;
+    omega = 1 / Fn;
+    return fabsl(step) < 1e-9L;
+}
+
+static bool newton_root(const Rec &r, int n, ld &t, ld lo, ld hi, bool near = false)
+{
+    // `near`: t is already within ~1e-11 of the root (double phase), so one
+    // step reaches long double accuracy and one more confirms it
     int extra = -1;
     for (int it = 0; it < 60; ++it) {
         ld pn, pn1, dpn;
@@ -178,24 +239,45 @@ static bool newton_root(const Rec &r, int n, ld &t, ld lo, ld hi)
         ld tn = t - step;
         if (!(tn > lo && tn < hi)) tn = (tn <= lo) ? 0.5L * (t + lo) : 0.5L * (t + hi);
         t = tn;
-        if (extra < 0 && fabsl(step) < 1e-14L) extra = 2;
+        if (extra < 0 && fabsl(step) < 1e-14L) extra = near ? 0 : 2;
         if (extra >= 0 && extra-- == 0) return true;
     }
     return false;
 }
 
-static void nodes_ld(const Rec &r, int n, ld a, ld b, std::vector<ld> &t)
+static void nodes_ld(const Rec &r, int n, ld a, ld b, std::vector<ld> &t, std::vector<ld> &om)
 {
     t.assign(n, 0);
+    om.assign(n, 0);
     const ld N = n + (a + b + 1) / 2;
     const ld cell = kPi / N;
     std::atomic<int> bad(0);
-    parallel_for(n, [&](int j) {
-        ld tj = (j + 1 + a / 2 - 0.25L) * cell;
-        ld lo = std::max<ld>(0, tj - cell), hi = std::min<ld>(kPi, tj + cell);
-        if (tj <= lo || tj >= hi) tj = 0.5L * (lo + hi);
-        if (!newton_root(r, n, tj, lo, hi)) bad.fetch_add(1);
-        t[j] = tj;
+    parallel_for((n + 7) / 8, [&](int g) {
+        const int j0 = 8 * g, cnt = std::min(8, n - j0);
+        ld tl[8], lol[8], hil[8];
+        double td[8], lod[8], hid[8];
+        bool conv[8];
+        for (int i = 0; i < cnt; ++i) {
+            ld tj = (j0 + i + 1 + a / 2 - 0.25L) * cell;
+            ld lo = std::max<ld>(0, tj - cell), hi = std::min<ld>(kPi, tj + cell);
+            if (tj <= lo || tj >= hi) tj = 0.5L * (lo + hi);
+            tl[i] = tj; lol[i] = lo; hil[i] = hi;
+            td[i] = (double)tj; lod[i] = (double)lo; hid[i] = (double)hi;
+        }
+        newton_double_group(r, n, cnt, td, lod, hid, conv);
+        for (int i = 0; i < cnt; ++i) {
+            ld tj = conv[i] ? (ld)td[i] : tl[i];
+            ld w = 0;
+            if (conv[i] && newton_final(r, n, a, b, tj, w) && tj > lol[i] && tj < hil[i]) {
+                t[j0 + i] = tj;
+                om[j0 + i] = w;
+                continue;
+            }
+            tj = tl[i];
+            if (!newton_root(r, n, tj, lol[i], hil[i])) bad.fetch_add(1);
+            t[j0 + i] = tj;
+            om[j0 + i] = weight_at(r, n, cosl(tj));
+        }
     });
     bool ok = bad.load() == 0;
     for (int j = 0; ok && j < n; ++j) {
@@ -231,6 +313,7 @@ static void nodes_ld(const Rec &r, int n, ld a, ld b, std::vector<ld> &t)
         }
         if (!newton_root(r, n, tj, lo - cell * 1e-6L, hi + cell * 1e-6L)) bad.fetch_add(1);
         t[j] = tj;
+        om[j] = weight_at(r, n, cosl(tj));
     });
 }
 
@@ -238,15 +321,13 @@ void gauss_jacobi(int n, double a, double b, std::vector<double> &t, std::vector
                   std::vector<double> &omega)
 {
     Rec r = recurrence(n, a, b);
-    std::vector<ld> tl;
-    nodes_ld(r, n, a, b, tl);
+    std::vector<ld> tl, wl;
+    nodes_ld(r, n, a, b, tl, wl);
     t.resize(n); x.resize(n); omega.resize(n);
     for (int j = 0; j < n; ++j) {
-        ld xj = cosl(tl[j]);
-        ld om = weight_at(r, n, xj);
         t[j] = (double)tl[j];
-        x[j] = (double)xj;
-        omega[j] = (double)om;
+        x[j] = (double)cosl(tl[j]);
+        omega[j] = (double)wl[j];
     }
 }
 
@@ -267,12 +348,11 @@ struct QuadTables {
     QuadTables()
     {
         Rec r = recurrence(16, 0, 0);
-        std::vector<ld> tl;
-        nodes_ld(r, 16, 0, 0, tl);
+        std::vector<ld> tl, wl;
+        nodes_ld(r, 16, 0, 0, tl, wl);
         for (int j = 0; j < 16; ++j) {
-            ld xj = cosl(tl[j]);
-            gl_x[j] = xj;
-            gl_w[j] = weight_at(r, 16, xj);  // Gauss-Legendre weights on [-1, 1]
+            gl_x[j] = cosl(tl[j]);
+            gl_w[j] = wl[j];  // Gauss-Legendre weights on [-1, 1]
         }
         // The far-end singularity (ell - v)^e with e close to -1 leaves the
         // transformed integrand decaying only like (1 - tau)^(1 + e); the
@@ -361,7 +441,7 @@ struct Evaluator {
         for (int k = 0; k <= kmax; ++k) {
             emit(k, p, q);
             if (k == kmax) break;
-            ld ib = 1 / rec.be[k + 1];
+            ld ib = rec.ibe[k + 1];
             ld pn = ((xj - rec.al[k]) * p - rec.be[k] * pm) * ib;
             ld qn = ((xj - rec.al[k]) * q - rec.be[k] * qm + (k == 0 ? rec.sqrt_mu0 : 0)) * ib;
             pm = p; p = pn;
@@ -380,9 +460,49 @@ struct Evaluator {
             if (k >= nu0) out[k - nu0] = entry(j, k, p, q);
         });
     }
+    // Sampled columns in double precision, 8 nodes walked side by side (the
+    // recurrence is a dependent chain; independent chains fill the pipeline).
+    // Used when the tolerance is far above the double-precision recurrence
+    // error (about 1e-14 at these degrees).
+    bool dbl_cols = false;
+    CMat cols_double(const std::vector<int> &cs) const
+    {
+        CMat out(n, (int)cs.size());
+        const int kmax = nu0 + cs.back();
+        const double p0 = (double)(1 / rec.sqrt_mu0), sm0 = (double)rec.sqrt_mu0;
+        parallel_for((n + 7) / 8, [&](int g) {
+            constexpr int G = 8;
+            const int j0 = 8 * g, cnt = std::min(G, n - j0);
+            double xx[G], pm[G], p[G], qm[G], q[G];
+            for (int i = 0; i < G; ++i) {
+                const int j = j0 + std::min(i, cnt - 1);
+                xx[i] = (double)x[j];
+                pm[i] = 0; p[i] = p0; qm[i] = 0; q[i] = (double)q0[j];
+            }
+            size_t ci = 0;
+            for (int k = 0; k <= kmax; ++k) {
+                while (ci < cs.size() && nu0 + cs[ci] == k) {
+                    for (int i = 0; i < cnt; ++i) out(j0 + i, (int)ci) = entry(j0 + i, k, p[i], q[i]);
+                    ++ci;
+                }
+                if (k == kmax) break;
+                const double ib = rec.ibe_d[k + 1], al = rec.al_d[k], bk = rec.be_d[k];
+                const double add = (k == 0) ? sm0 : 0.0;
+                for (int i = 0; i < G; ++i) {
+                    const double xa = xx[i] - al;
+                    const double pn = (xa * p[i] - bk * pm[i]) * ib;
+                    const double qn = (xa * q[i] - bk * qm[i] + add) * ib;
+                    pm[i] = p[i]; p[i] = pn;
+                    qm[i] = q[i]; q[i] = qn;
+                }
+            }
+        });
+        return out;
+    }
     // columns (degree offsets c = k - nu0), sorted ascending
     CMat cols(const std::vector<int> &cs) const
     {
+        if (dbl_cols && !cs.empty()) return cols_double(cs);
         CMat out(n, (int)cs.size());
         if (cs.empty()) return out;
         int kmax = nu0 + cs.back();
@@ -416,13 +536,13 @@ static void rsvd(const Evaluator &E, double tol, const PlanOptions &opt, uint64_
     const int rmax = std::min(Nr, Nc);
     int r = std::min(rmax, std::max(4, (int)std::ceil(2.0 * std::log2((double)E.n))));
     Rng rng(seed);
-    const bool all_rows = Nr <= 4096;
+    const bool all_rows = Nr <= 2048;
     std::vector<int> check_rows;
     if (all_rows) {
         check_rows.resize(Nr);
         std::iota(check_rows.begin(), check_rows.end(), 0);
     } else {
-        check_rows = sample(rng, Nr, 256, {});
+        check_rows = sample(rng, Nr, 512, {});
     }
     const CMat Zc = E.rows(check_rows);
     double zc2 = 0.0;
@@ -556,8 +676,8 @@ void build_axis(AxisPlan &ax, int n, double a, double b, double tol, const PlanO
     ax.seed = opt.seed ? opt.seed : mix_key(n, a, b, tol);
 
     Rec rec = recurrence(n + 1, a, b);
-    std::vector<ld> tl;
-    nodes_ld(rec, n, a, b, tl);
+    std::vector<ld> tl, wl;
+    nodes_ld(rec, n, a, b, tl, wl);
     Evaluator E;
     E.n = n; E.nu0 = ax.nu0; E.L = L; E.Nc = n - ax.nu0; E.rec = rec;
     E.x.resize(n); E.sw.resize(n); E.invpw.resize(n); E.q0.resize(n); E.m.resize(n);
@@ -565,7 +685,7 @@ void build_axis(AxisPlan &ax, int n, double a, double b, double tol, const PlanO
     parallel_for(n, [&](int j) {
         ld t = tl[j];
         ld xj = cosl(t);
-        ld om = weight_at(rec, n, xj);
+        ld om = wl[j];
         ld sh = sinl(t / 2), ch = cosl(t / 2);
         ld omx = 2 * sh * sh, opx = 2 * ch * ch;  // 1 - x, 1 + x without cancellation
         ld wx = powl(omx, (ld)a) * powl(opx, (ld)b);
@@ -603,6 +723,7 @@ void build_axis(AxisPlan &ax, int n, double a, double b, double tol, const PlanO
         ld ang = -2 * kPi * p / L;
         E.ph[p] = cd((double)cosl(ang), (double)sinl(ang));
     }
+    E.dbl_cols = tol >= 1e-10;
     if (E.Nc > 0)
         rsvd(E, tol, opt, ax.seed, ax);
 }
@@ -621,7 +742,7 @@ void exact_entries(const AxisPlan &ax, int count, const int *rows, const int *de
         ld q = hilbert_weight_parts(omx, opx, ax.a, ax.b) / rec.sqrt_mu0;
         ld pm = 0, p = 1 / rec.sqrt_mu0, qm = 0;
         for (int kk = 0; kk < k; ++kk) {
-            ld ib = 1 / rec.be[kk + 1];
+            ld ib = rec.ibe[kk + 1];
             ld pn = ((xj - rec.al[kk]) * p - rec.be[kk] * pm) * ib;
             ld qn = ((xj - rec.al[kk]) * q - rec.be[kk] * qm + (kk == 0 ? rec.sqrt_mu0 : 0)) * ib;
             pm = p; p = pn;

@@ -21,14 +21,14 @@ def declared_functions():
 def test_every_declared_symbol_is_exported():
     lib = ctypes.CDLL(jt.LIB_PATH)
     names = declared_functions()
-    assert len(names) >= 17
+    assert len(names) >= 27
     for name in names:
         assert hasattr(lib, name), name
     assert set(jt.SYMBOLS) | {"jt_last_error", "jt_version"} >= set(names)
 
 
 def test_version():
-    assert jt.version() == 100
+    assert jt.version() == 110
 
 
 @pytest.mark.parametrize("n,ab,tol", [
