@@ -177,19 +177,23 @@ def batched(args) -> int:
         ref = oracle.forward(x32, abs_[i])
         g = got[offs[i]:offs[i] + sizes[i]].reshape(shapes[i])
         errs.append(float(np.linalg.norm(g - ref) / np.linalg.norm(ref)))
-    # the plain fp64 path on the same GPU: the same items one transform at a time
-    dev_x = [torch.from_numpy(x).to(dev) for x in xs]
+    # the plain fp64 path on the same GPU: the same items one transform at a
+    # time (items it supports: n <= 8192 per axis), and the batch restricted
+    # to those items for a like-for-like ratio
+    sel = [i for i, s in enumerate(shapes) if max(s) <= 8192]
+    dev_x = [torch.from_numpy(xs[i]).to(dev) for i in sel]
     dev_g = [torch.empty_like(x) for x in dev_x]
-    for p, x, g in zip(plans, dev_x, dev_g):
-        p.forward(x, g, prec=jt.PREC_FP64)
+    for i, x, g in zip(sel, dev_x, dev_g):
+        plans[i].forward(x, g, prec=jt.PREC_FP64)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    for p, x, g in zip(plans, dev_x, dev_g):
-        p.forward(x, g, prec=jt.PREC_FP64)
+    for i, x, g in zip(sel, dev_x, dev_g):
+        plans[i].forward(x, g, prec=jt.PREC_FP64)
     e1.record(stream)
     torch.cuda.synchronize()
     t64 = e0.elapsed_time(e1)
+    coeffs_sel = int(sum(sizes[i] for i in sel))
     info = B.info()
     line = {
         "metric": "coeffs/s, ragged batch of %d independent %s transforms in one persistent launch"
@@ -204,10 +208,185 @@ def batched(args) -> int:
                      "frac": achieved / 8000.0, "traffic": None, "kernel": "batch_kernel<float>",
                      "bytes_per_launch": nbytes},
         "sample_rel_l2_max": max(errs) if errs else None,
-        "fp64_one_at_a_time": {"ms": t64, "value": coeffs / (t64 * 1e-3), "launches": int(sum(len(s) for s in shapes))},
+        "fp64_one_at_a_time": {"ms": t64, "value": coeffs_sel / (t64 * 1e-3), "items": len(sel),
+                               "launches": int(sum(len(shapes[i]) for i in sel))},
     }
     print(json.dumps(line))
     del arena
+    return 0
+
+
+class PinnedPool:
+    """First-fit allocator over one pinned host buffer (float32 elements), so
+    that request inputs and outputs can be copied asynchronously."""
+
+    def __init__(self, torch, elems: int):
+        self.buf = torch.empty(elems, dtype=torch.float32, pin_memory=True).numpy()
+        self.free = [(0, elems)]
+
+    def alloc(self, n: int):
+        for i, (o, sz) in enumerate(self.free):
+            if sz >= n:
+                if sz == n:
+                    self.free.pop(i)
+                else:
+                    self.free[i] = (o + n, sz - n)
+                return o
+        return None
+
+    def release(self, o: int, n: int):
+        self.free.append((o, n))
+        self.free.sort()
+        merged = []
+        for a, b in self.free:
+            if merged and merged[-1][0] + merged[-1][1] == a:
+                merged[-1] = (merged[-1][0], merged[-1][1] + b)
+            else:
+                merged.append((a, b))
+        self.free = merged
+
+
+def serve_stream(jt, S, reqs, data, arrivals, pool):
+    """Submit `reqs` to server S at the given arrival times (None: all at
+    once), wait for all, return (wall seconds, per-request infos, stats delta)."""
+    import threading
+
+    before = S.stats()
+    pending = []
+    lock = threading.Condition()
+    infos = [None] * len(reqs)
+    done_count = [0]
+
+    def waiter():
+        k = 0
+        while k < len(reqs):
+            with lock:
+                while k >= len(pending):
+                    lock.wait()
+                t, i, oi, oo, n = pending[k]
+            infos[i] = S.wait(t)
+            with lock:
+                pool.release(oi, n)
+                pool.release(oo, n)
+                done_count[0] += 1
+                lock.notify_all()
+            k += 1
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    t0 = jt.clock()
+    for i, (d, shape, ab, direction) in enumerate(reqs):
+        if arrivals is not None:
+            delay = t0 + arrivals[i] - jt.clock()
+            if delay > 0:
+                time.sleep(delay)
+        n = int(np.prod(shape))
+        with lock:
+            while True:
+                oi = pool.alloc(n)
+                oo = pool.alloc(n) if oi is not None else None
+                if oo is not None:
+                    break
+                if oi is not None:
+                    pool.release(oi, n)
+                lock.wait()
+        x = pool.buf[oi:oi + n].reshape(shape)
+        off = (i * 7919) % (len(data) - n)
+        x[...] = data[off:off + n].reshape(shape)
+        out = pool.buf[oo:oo + n].reshape(shape)
+        t = S.submit(x, out, ab, direction)
+        with lock:
+            pending.append((t, i, oi, oo, n))
+            lock.notify_all()
+    th.join()
+    wall = jt.clock() - t0
+    after = S.stats()
+    stats = {k: (after[k] - before[k]) if k in ("plan_hits", "plan_misses", "launches", "completed", "failed",
+                                                    "plans_evicted") else after[k] for k in after}
+    return wall, infos, stats
+
+
+def serving(args) -> int:
+    """The mixed serving stream: continuous batching with plan caching and
+    HBM-footprint admission; p50/p99 latency (submit to output on the host)
+    at offered loads below saturation, against the fp64 single-transform path."""
+    import torch
+
+    import paper_1901_07275_amd as jt
+
+    reqs_all = workloads.serving_stream(args.count + args.warm, seed=105)
+    warm, reqs = reqs_all[:args.warm], reqs_all[args.warm:]
+    data = np.random.default_rng(107).standard_normal(1 << 25).astype(np.float32)
+    pool = PinnedPool(torch, 1 << 29)  # 2 GiB of pinned host buffers
+    arena = 16 << 30
+    S = jt.Server(arena, tol=1e-7, prec=jt.PREC_FP32_BULK, dtype=jt.F32)
+    print("warm-up %d requests" % len(warm), file=sys.stderr, flush=True)
+    serve_stream(jt, S, warm, data, None, pool)
+    # first pass over the measured requests, all offered at once: their plans
+    # are mostly cold (built on the host while the stream runs)
+    print("cold saturation run", file=sys.stderr, flush=True)
+    wall_c, infos_c, st_c = serve_stream(jt, S, reqs, data, None, pool)
+    lat_c = np.array([i["t_done"] - i["t_submit"] for i in infos_c])
+    cold_c = np.array([i["cold"] for i in infos_c], dtype=bool)
+    plan_s = np.array([i["plan_seconds"] for i in infos_c])
+    # warm saturation: the same requests again, plans cached
+    print("warm saturation run", file=sys.stderr, flush=True)
+    wall, infos, st = serve_stream(jt, S, reqs, data, None, pool)
+    coeffs = float(sum(int(np.prod(r[1])) for r in reqs))
+    sat_rps = len(reqs) / wall
+    runs = []
+    for frac in args.rates:
+        rate = frac * sat_rps
+        arr = workloads.poisson_arrivals(len(reqs), rate, seed=106)
+        print("rate %.2f x saturation (%.1f req/s)" % (frac, rate), file=sys.stderr, flush=True)
+        w, inf, stt = serve_stream(jt, S, reqs, data, arr, pool)
+        lat = np.array([i["t_done"] - i["t_submit"] for i in inf])
+        runs.append({"load": frac, "rate_rps": rate, "wall_s": w, "coeffs_per_s": coeffs / w,
+                     "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                     "plan_hit_rate": stt["plan_hits"] / max(1, stt["plan_hits"] + stt["plan_misses"]),
+                     "launches": stt["launches"], "arena_peak_bytes": stt["arena_peak"]})
+    S.close()
+    # the plain fp64 path on the same GPU: the same requests, one at a time,
+    # plans built beforehand (planning excluded), host in -> host out
+    dev = torch.device("cuda:0")
+    sub = reqs[:args.fp64_count]
+    plans = jt.plan_many([r[1] for r in sub], [r[2] for r in sub], 1e-7)
+    lat64 = []
+    t0 = time.perf_counter()
+    for (d, shape, ab, direction), p in zip(sub, plans):
+        p.bind(dev)
+        n = int(np.prod(shape))
+        x = data[:n].astype(np.float64).reshape(shape)
+        t1 = time.perf_counter()
+        xt = torch.from_numpy(x).to(dev)
+        g = p.forward(xt, prec=jt.PREC_FP64) if direction == 0 else p.inverse(xt, prec=jt.PREC_FP64)
+        g.cpu()
+        lat64.append(time.perf_counter() - t1)
+    t64 = time.perf_counter() - t0
+    c64 = float(sum(int(np.prod(r[1])) for r in sub))
+    best = max(runs, key=lambda r: r["coeffs_per_s"]) if runs else None
+    line = {
+        "metric": "coeffs/s and p50/p99 latency, mixed serving stream (d = 1/2/3) with continuous batching",
+        "value": coeffs / wall, "unit": "coeffs/s", "n_gpus": 1, "steps": len(reqs), "warmup": len(warm),
+        "ms_per_step": wall / len(reqs) * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "serving", "requests": len(reqs), "coeffs": coeffs, "tol": 1e-7,
+                   "arena_bytes": arena, "warm_saturation_rps": sat_rps, "warm_saturation_launches": st["launches"]},
+        "cold_pass": {"wall_s": wall_c, "coeffs_per_s": coeffs / wall_c,
+                      "plan_hit_rate": st_c["plan_hits"] / max(1, st_c["plan_hits"] + st_c["plan_misses"]),
+                      "cold_fraction": float(cold_c.mean()),
+                      "cold_p50_ms": float(np.percentile(lat_c[cold_c], 50) * 1e3) if cold_c.any() else None,
+                      "warm_p50_ms": float(np.percentile(lat_c[~cold_c], 50) * 1e3) if (~cold_c).any() else None,
+                      "plan_seconds_p50": float(np.percentile(plan_s[cold_c], 50)) if cold_c.any() else None},
+        "loads": runs,
+        "fp64_one_at_a_time": {"requests": len(sub), "coeffs_per_s": c64 / t64,
+                               "p50_ms": float(np.percentile(lat64, 50) * 1e3),
+                               "p99_ms": float(np.percentile(lat64, 99) * 1e3),
+                               "note": "plans prebuilt; host fp64 in and out"},
+    }
+    if best is not None:
+        line["p50_ms"], line["p99_ms"] = best["p50_ms"], best["p99_ms"]
+    print(json.dumps(line))
     return 0
 
 
@@ -218,9 +397,13 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--workload", default="2d", choices=["2d", "batched-1d", "batched-2d"],
+    ap.add_argument("--warm", type=int, default=200, help="serving: warm-up requests")
+    ap.add_argument("--rates", type=lambda v: [float(x) for x in v.split(",")], default=[0.5, 0.8, 0.95],
+                    help="serving: offered loads as fractions of the measured saturation rate")
+    ap.add_argument("--fp64-count", type=int, default=200, help="serving: requests timed on the fp64 path")
+    ap.add_argument("--workload", default="2d", choices=["2d", "batched-1d", "batched-2d", "serving"],
                     help="2d: the 1024 x 1024 forward + inverse headline; batched-*: ragged batches")
-    ap.add_argument("--count", type=int, default=4096, help="items of a batched workload")
+    ap.add_argument("--count", type=int, default=4096, help="items of a batched workload (serving: requests)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times), to calibrate "
                          "rocprofv3 FETCH_SIZE/WRITE_SIZE against known bytes")
@@ -242,6 +425,8 @@ def main() -> int:
         print(json.dumps({"copy_probe_bytes": nbytes, "launches": 5}))
         return 0
 
+    if args.workload == "serving":
+        return serving(args)
     if args.workload != "2d":
         return batched(args)
 

@@ -252,6 +252,65 @@ jt_status jt_batch_replay(jt_batch_t batch, void *stream);
  * for its previous pass timed out, bit 1 = unsupported length. 0 = clean. */
 jt_status jt_batch_errors(jt_batch_t batch, void *stream, uint32_t *flags);
 
+/* ----------------------------------------------------------------------
+ * Serving form: a request loop with continuous batching.  Requests carry
+ * host input and output buffers (pinned memory lets the copies overlap).  A
+ * scheduler thread admits them in arrival order while the device arena has
+ * room for their input and output (HBM-footprint admission), copies them in,
+ * and launches every admitted request whose axis plans are resident as one
+ * persistent batch launch; requests arriving meanwhile go into the next
+ * launch as memory frees up.  Axis plans are cached in the arena keyed by
+ * (n, a, b, tol), built on host threads on a miss and evicted least recently
+ * used.  A request's result does not depend on the other requests it runs
+ * with.  The arena is caller-owned device memory the server sub-allocates.
+ */
+typedef struct jt_server_s *jt_server_t;
+
+typedef struct {
+    double tol;              /* low-rank tolerance of every plan; 0 = 1e-7 */
+    int prec;                /* jt_prec; default JT_PREC_FP64 (0): pass JT_PREC_FP32_BULK for the fp32 form */
+    int in_dtype, out_dtype; /* jt_dtype of request data; default JT_F64 (0) */
+    int max_batch;           /* most requests per launch; 0 = 256 */
+    int max_inflight;        /* launches in flight; 0 = 2 */
+    int plan_threads;        /* host planning threads; 0 = hardware threads (at most 16) */
+    jt_batch_options batch;  /* unit shaping of each launch */
+} jt_server_options;
+
+typedef struct {
+    int state;               /* 0 queued, 1 admitted, 2 running, 3 done, 4 failed */
+    int cold;                /* one of its axis plans was built for it (cache miss) */
+    double t_submit, t_admit, t_launch, t_done;  /* jt_clock() seconds */
+    double plan_seconds;     /* host planning time of its missed plans */
+    int status;              /* jt_status of a failed request */
+} jt_request_info;
+
+typedef struct {
+    uint64_t submitted, completed, failed;
+    uint64_t plan_hits, plan_misses, plans_cached, plans_evicted;
+    uint64_t launches;
+    double coeffs;           /* coefficients of completed requests */
+    size_t arena_bytes, arena_used, arena_peak;
+    int queued, admitted, running;
+} jt_server_stats;
+
+/* Monotonic clock (seconds) the server stamps requests with. */
+double jt_clock(void);
+/* dev_arena: caller-owned device memory, 256-byte aligned, kept until destroy.
+ * Errors: JT_EINVAL, JT_EDEVICE. */
+jt_status jt_server_create(void *dev_arena, size_t bytes, const jt_server_options *opt, jt_server_t *server);
+/* Queue one transform of a d-dimensional row-major tensor.  host_in and
+ * host_out must stay valid until the request is done.  Errors: JT_EINVAL,
+ * JT_ENOMEM (input and output alone exceed the arena), JT_EUNSUPPORTED. */
+jt_status jt_server_submit(jt_server_t server, int d, const int *n, const double *a, const double *b,
+                           jt_direction dir, const void *host_in, void *host_out, uint64_t *ticket);
+/* State and timestamps of a request (non-blocking). */
+jt_status jt_server_poll(jt_server_t server, uint64_t ticket, jt_request_info *info);
+/* Block until the request is done or failed, return its info and forget the ticket. */
+jt_status jt_server_wait(jt_server_t server, uint64_t ticket, jt_request_info *info);
+jt_status jt_server_stats_get(jt_server_t server, jt_server_stats *stats);
+/* Finish running launches, fail queued requests, release host resources. */
+jt_status jt_server_destroy(jt_server_t server);
+
 /* Message describing the last error on the calling thread ("" if none). */
 const char *jt_last_error(void);
 

@@ -21,7 +21,26 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(
         "libjt.so not found at %s; build it with `python paper_1901_07275_amd/build.py`" % LIB_PATH)
 
+# torch first: libjt.so then binds to the HIP runtime torch already loaded
+# (same soname), so tensors, streams and kernels share one runtime.  Loading
+# libjt.so first would bring in a second HIP/HSA runtime beside torch's.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
+
+
+def _hip_runtimes() -> set:
+    """Paths of the HIP runtime libraries mapped into this process."""
+    try:
+        with open("/proc/self/maps") as f:
+            return {line.split()[-1] for line in f if "libamdhip64" in line}
+    except OSError:
+        return set()
+
+
+if len(_hip_runtimes()) > 1:
+    raise ImportError("two HIP runtimes are loaded (%s); import torch before anything that loads "
+                      "/opt/rocm's libamdhip64" % ", ".join(sorted(_hip_runtimes())))
 
 JT_OK, JT_EINVAL, JT_ENOMEM, JT_EDEVICE, JT_ENOTCONV, JT_EUNSUPPORTED, JT_ESTATE = range(7)
 F64, F32 = 0, 1
@@ -49,6 +68,27 @@ class BatchOptions(ctypes.Structure):
 class BatchInfo(ctypes.Structure):
     _fields_ = [("units", ctypes.c_int), ("passes", ctypes.c_int), ("grid", ctypes.c_int),
                 ("threads", ctypes.c_int), ("lds_bytes", ctypes.c_size_t), ("cost", ctypes.c_double)]
+
+
+class ServerOptions(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("prec", ctypes.c_int), ("in_dtype", ctypes.c_int),
+                ("out_dtype", ctypes.c_int), ("max_batch", ctypes.c_int), ("max_inflight", ctypes.c_int),
+                ("plan_threads", ctypes.c_int), ("batch", BatchOptions)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int), ("cold", ctypes.c_int), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_launch", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("plan_seconds", ctypes.c_double), ("status", ctypes.c_int)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+                ("plan_hits", ctypes.c_uint64), ("plan_misses", ctypes.c_uint64),
+                ("plans_cached", ctypes.c_uint64), ("plans_evicted", ctypes.c_uint64),
+                ("launches", ctypes.c_uint64), ("coeffs", ctypes.c_double), ("arena_bytes", ctypes.c_size_t),
+                ("arena_used", ctypes.c_size_t), ("arena_peak", ctypes.c_size_t), ("queued", ctypes.c_int),
+                ("admitted", ctypes.c_int), ("running", ctypes.c_int)]
 
 
 _vp = ctypes.c_void_p
@@ -87,6 +127,12 @@ SYMBOLS = {
     "jt_batch_capture": [_vp, _vp, _vp],
     "jt_batch_replay": [_vp, _vp],
     "jt_batch_errors": [_vp, _vp, ctypes.POINTER(ctypes.c_uint32)],
+    "jt_server_create": [_vp, ctypes.c_size_t, ctypes.POINTER(ServerOptions), ctypes.POINTER(_vp)],
+    "jt_server_submit": [_vp, ctypes.c_int, _ip, _dp, _dp, ctypes.c_int, _vp, _vp, ctypes.POINTER(ctypes.c_uint64)],
+    "jt_server_poll": [_vp, ctypes.c_uint64, ctypes.POINTER(RequestInfo)],
+    "jt_server_wait": [_vp, ctypes.c_uint64, ctypes.POINTER(RequestInfo)],
+    "jt_server_stats_get": [_vp, ctypes.POINTER(ServerStats)],
+    "jt_server_destroy": [_vp],
 }
 for _name, _args in SYMBOLS.items():
     _f = getattr(_lib, _name)
@@ -96,6 +142,13 @@ _lib.jt_last_error.restype = ctypes.c_char_p
 _lib.jt_last_error.argtypes = []
 _lib.jt_version.restype = ctypes.c_int
 _lib.jt_version.argtypes = []
+_lib.jt_clock.restype = ctypes.c_double
+_lib.jt_clock.argtypes = []
+
+
+def clock() -> float:
+    """The monotonic clock (seconds) the server stamps requests with."""
+    return _lib.jt_clock()
 
 
 class JTError(RuntimeError):
@@ -423,3 +476,77 @@ class Batch:
         v = ctypes.c_uint32()
         _check(_lib.jt_batch_errors(self._h, _vp(st.cuda_stream), ctypes.byref(v)))
         return v.value
+
+
+# ---------------------------------------------------------------- serving
+def _info_dict(inf: RequestInfo) -> dict:
+    return {f: getattr(inf, f) for f, _ in RequestInfo._fields_}
+
+
+class Server:
+    """Continuous-batching request loop over a device arena (jt_server_*).
+
+    arena_bytes of device memory are allocated with torch and handed to the
+    server, which sub-allocates request buffers, cached axis plans and launch
+    tables in it.  submit() takes host numpy arrays (pinned memory lets the
+    copies overlap); the output array must stay alive until wait() returns."""
+
+    def __init__(self, arena_bytes: int, tol: float = 1e-7, prec: int = PREC_FP32_BULK, dtype: int = F32,
+                 max_batch: int = 0, max_inflight: int = 0, plan_threads: int = 0, device=None,
+                 max_split: int = 0, min_units: int = 0, grid: int = 0):
+        import torch
+
+        device = torch.device(device or "cuda")
+        self._arena = torch.empty(int(arena_bytes) + 256, dtype=torch.uint8, device=device)
+        base = self._arena.data_ptr() + (-self._arena.data_ptr()) % 256
+        torch.cuda.synchronize(device)
+        opt = ServerOptions(float(tol), int(prec), int(dtype), int(dtype), int(max_batch), int(max_inflight),
+                            int(plan_threads), BatchOptions(int(max_split), int(min_units), int(grid)))
+        h = _vp()
+        _check(_lib.jt_server_create(_vp(base), int(arena_bytes), ctypes.byref(opt), ctypes.byref(h)))
+        self._h = h
+        self.dtype = np.float64 if dtype == F64 else np.float32
+        self._keep = {}
+
+    def submit(self, x: np.ndarray, out: np.ndarray, ab, direction: int = FORWARD) -> int:
+        x = np.asarray(x)
+        if x.dtype != self.dtype or out.dtype != self.dtype or not x.flags.c_contiguous or not out.flags.c_contiguous:
+            raise TypeError("input and output must be C-contiguous %s arrays" % np.dtype(self.dtype).name)
+        if x.shape != out.shape:
+            raise ValueError("input and output shapes differ")
+        d = x.ndim
+        if len(ab) != d:
+            raise ValueError("need one (a, b) pair per axis")
+        t = ctypes.c_uint64()
+        _check(_lib.jt_server_submit(self._h, d, (ctypes.c_int * d)(*x.shape),
+                                     (ctypes.c_double * d)(*[float(p[0]) for p in ab]),
+                                     (ctypes.c_double * d)(*[float(p[1]) for p in ab]), int(direction),
+                                     _vp(x.ctypes.data), _vp(out.ctypes.data), ctypes.byref(t)))
+        self._keep[t.value] = (x, out)
+        return t.value
+
+    def poll(self, ticket: int) -> dict:
+        inf = RequestInfo()
+        _check(_lib.jt_server_poll(self._h, ticket, ctypes.byref(inf)))
+        return _info_dict(inf)
+
+    def wait(self, ticket: int) -> dict:
+        inf = RequestInfo()
+        st = _lib.jt_server_wait(self._h, ticket, ctypes.byref(inf))
+        self._keep.pop(ticket, None)
+        _check(st)
+        return _info_dict(inf)
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check(_lib.jt_server_stats_get(self._h, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.jt_server_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        self.close()

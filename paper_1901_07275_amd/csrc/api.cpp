@@ -69,7 +69,6 @@ jt_status run_axis(jt_plan_t p, int axis, bool forward, const void *in, jt_dtype
     a.bins = reinterpret_cast<const int *>(d + ax.off_bins);
     a.binptr = reinterpret_cast<const int *>(d + ax.off_binptr);
     a.wv = d + (f32 ? ax.off_wv32 : ax.off_wv64);
-    a.wvt = d + (f32 ? ax.off_wvt32 : ax.off_wvt64);
     a.u = d + (f32 ? ax.off_u32 : ax.off_u64);
     a.v = d + (f32 ? ax.off_v32 : ax.off_v64);
     if (!f32 && ax.L > 8192) return fail(JT_EUNSUPPORTED, "fp64 path supports n <= 8192");
@@ -135,7 +134,7 @@ jt_plan_s *build_plan(int d, const int *n, const double *a, const double *b, dou
 
 extern "C" {
 
-int jt_version(void) { return 110; }
+int jt_version(void) { return 120; }
 
 const char *jt_last_error(void) { return g_err.c_str(); }
 

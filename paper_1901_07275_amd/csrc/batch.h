@@ -33,7 +33,6 @@ struct PassDesc {
     const int *bins = nullptr;
     const int *binptr = nullptr;
     const void *wv = nullptr;
-    const void *wvt = nullptr;
     const void *u = nullptr;
     const void *v = nullptr;
 };

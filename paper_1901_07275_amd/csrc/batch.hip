@@ -63,7 +63,6 @@ __device__ __attribute__((noinline)) void run_unit(const PassDesc &d, const Work
         a.bins = d.bins;
         a.binptr = d.binptr;
         a.wv = d.wv;
-        a.wvt = d.wvt;
         a.u = d.u;
         a.v = d.v;
         const int S = w.split;

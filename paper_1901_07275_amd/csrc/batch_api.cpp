@@ -13,26 +13,19 @@
 
 #include "batch.h"
 #include "handle.h"
+#include "queue.h"
 #include "threads.h"
 
 using jt::fail;
 using jt::ok;
 
 struct jt_batch_s {
-    struct Item {
-        jt_plan_t plan;
-        int dir;
-        uint64_t in_off, out_off;
-    };
-    std::vector<Item> items;
-    std::vector<jt::PassDesc> passes;
-    std::vector<jt::WorkUnit> units;
-    std::vector<int32_t> pass_item, pass_axis;
+    std::vector<jt_plan_t> plans;
+    std::vector<jt::QueueItem> items;
+    jt::WorkQueue q;
     bool fp32 = true;
     jt_dtype tin = JT_F64, tout = JT_F64;
     jt_batch_options opt{};
-    double cost = 0;
-    size_t off_units = 0, off_passes = 0, off_counters = 0, bytes = 0;
     unsigned char *dev = nullptr;
     int grid = 0;
     hipGraph_t graph = nullptr;
@@ -45,37 +38,6 @@ struct jt_batch_s {
     }
 };
 
-namespace {
-
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-int pow2_at_least(int v)
-{
-    int p = 1;
-    while (p < v) p *= 2;
-    return p;
-}
-
-// Split S for a pass: S groups share each line set, so a unit holds
-// (groups / S) * LPB lines.  Lines beyond what the pass has would leave
-// groups idle, so S grows until the unit's capacity fits the lines (a single
-// line gets every group); it never exceeds the groups, the rank (rounded up to
-// a power of two) or the option's cap.  min_units raises S further while the
-// pass has fewer units than asked for.
-int choose_split(int L, int lines, int rank, const jt_batch_options &o, bool fp32)
-{
-    const int NT = jt::batch_threads(fp32);
-    const int gt = jt::group_threads(L), lpb = jt::group_lines(L);
-    const int groups = NT / gt;
-    const int cap = std::max(1, std::min({groups, o.max_split > 0 ? o.max_split : 16, pow2_at_least(std::max(rank, 1))}));
-    int S = 1;
-    while (S < cap && (groups / S) * lpb > lines) S *= 2;
-    const int want = std::max(1, o.min_units);
-    while (S < cap && (lines + (groups / S) * lpb - 1) / ((groups / S) * lpb) < want) S *= 2;
-    return S;
-}
-
-}  // namespace
 
 extern "C" {
 
@@ -150,80 +112,19 @@ jt_status jt_batch_create(int count, const jt_plan_t *plans, const int *dirs, co
         B->tout = tout;
         if (opt) B->opt = *opt;
         if (B->opt.max_split < 0 || B->opt.min_units < 0 || B->opt.grid < 0) return fail(JT_EINVAL, "negative option");
-        const size_t isz = tin == JT_F64 ? 8 : 4, osz = tout == JT_F64 ? 8 : 4;
-        struct Pending {
-            int pass_in_item;
-            jt::WorkUnit u;
-            double cost;
-        };
-        std::vector<Pending> pend;
         for (int i = 0; i < count; ++i) {
             jt_plan_t p = plans[i];
             if (!p) return fail(JT_EINVAL, "item " + std::to_string(i) + ": null plan");
-            if (dirs[i] != JT_FORWARD && dirs[i] != JT_INVERSE) return fail(JT_EINVAL, "item " + std::to_string(i) + ": bad direction");
-            if (in_off[i] % isz || out_off[i] % osz) return fail(JT_EINVAL, "item " + std::to_string(i) + ": misaligned offset");
-            long long total = 1;
-            for (int k = 0; k < p->d; ++k) total *= p->ax[k].n;
-            if (total >= (1LL << 31)) return fail(JT_EUNSUPPORTED, "item " + std::to_string(i) + ": 2^31 elements or more");
-            B->items.push_back({p, dirs[i], in_off[i], out_off[i]});
-            // axes d-1 .. 0; the first pass reads the input, later ones work in place on the output
-            int prev = -1, prev_units = 0;
-            for (int k = p->d - 1, q = 0; k >= 0; --k, ++q) {
-                const jt::AxisPlan &ax = p->ax[k];
-                if (!B->fp32 && ax.L > 8192) return fail(JT_EUNSUPPORTED, "item " + std::to_string(i) + ": fp64 path supports n <= 8192");
-                long long stride = 1;
-                for (int m = k + 1; m < p->d; ++m) stride *= p->ax[m].n;
-                jt::PassDesc d;
-                d.in_off = q == 0 ? in_off[i] : out_off[i];
-                d.out_off = out_off[i];
-                d.in_from_out = q == 0 ? 0 : 1;
-                d.in_f64 = (q == 0 ? tin : tout) == JT_F64;
-                d.out_f64 = tout == JT_F64;
-                d.lines = (int32_t)(total / ax.n);
-                d.stride = (int32_t)stride;
-                d.n = ax.n;
-                d.L = ax.L;
-                d.nu0 = ax.nu0;
-                d.rank = ax.rank;
-                d.max_per_bin = ax.max_per_bin;
-                d.forward = dirs[i] == JT_FORWARD;
-                const int pid = (int)B->passes.size();
-                B->passes.push_back(d);
-                B->pass_item.push_back(i);
-                B->pass_axis.push_back(k);
-                const int S = choose_split(ax.L, d.lines, ax.rank, B->opt, B->fp32);
-                const int cap = (jt::batch_threads(B->fp32) / jt::group_threads(ax.L) / S) * jt::group_lines(ax.L);
-                const int nu = (d.lines + cap - 1) / cap;
-                // work of one unit: its share of the rank FFTs plus the direct block, per line set
-                const double per_term = (double)ax.L * std::log2((double)ax.L);
-                const double c = ((ax.rank + S - 1) / S) * per_term * 5.0 + 2.0 * ax.nu0 * ax.n + 4.0 * ax.n;
-                for (int u = 0; u < nu; ++u) {
-                    jt::WorkUnit w;
-                    w.pass = pid;
-                    w.line0 = u * cap;
-                    w.nlines = std::min(cap, d.lines - u * cap);
-                    w.split = S;
-                    w.wait_pass = prev;
-                    w.wait_count = prev < 0 ? 0 : prev_units;
-                    pend.push_back({q, w, c});
-                    B->cost += c;
-                }
-                prev = pid;
-                prev_units = nu;
-            }
+            jt::QueueItem it;
+            it.d = p->d;
+            for (int k = 0; k < p->d; ++k) it.ax[k] = &p->ax[k];
+            it.dir = dirs[i];
+            it.in_off = in_off[i];
+            it.out_off = out_off[i];
+            B->plans.push_back(p);
+            B->items.push_back(it);
         }
-        // queue order: every first pass, then every second pass, then third;
-        // within a rank the costliest units first (longest-processing-time rule)
-        std::stable_sort(pend.begin(), pend.end(), [](const Pending &x, const Pending &y) {
-            if (x.pass_in_item != y.pass_in_item) return x.pass_in_item < y.pass_in_item;
-            return x.cost > y.cost;
-        });
-        if (pend.size() >= (size_t)1 << 30) return fail(JT_EUNSUPPORTED, "too many work units");
-        for (const Pending &p : pend) B->units.push_back(p.u);
-        B->off_units = 0;
-        B->off_passes = align256(B->units.size() * sizeof(jt::WorkUnit));
-        B->off_counters = B->off_passes + align256(B->passes.size() * sizeof(jt::PassDesc));
-        B->bytes = B->off_counters + align256((2 + B->passes.size()) * sizeof(uint32_t));
+        jt::build_queue(B->items, B->opt, B->fp32, tin, tout, B->q);
         *batch = hold.release();
         return ok();
     });
@@ -238,31 +139,32 @@ jt_status jt_batch_destroy(jt_batch_t batch)
 jt_status jt_batch_info_get(jt_batch_t batch, jt_batch_info *info)
 {
     if (!batch || !info) return fail(JT_EINVAL, "null argument");
-    info->units = (int)batch->units.size();
-    info->passes = (int)batch->passes.size();
+    info->units = (int)batch->q.units.size();
+    info->passes = (int)batch->q.passes.size();
     info->grid = batch->grid;
     info->threads = jt::batch_threads(batch->fp32);
     info->lds_bytes = jt::batch_lds_bytes(batch->fp32);
-    info->cost = batch->cost;
+    info->cost = batch->q.cost;
     return ok();
 }
 
 jt_status jt_batch_tables(jt_batch_t batch, int32_t *units, int32_t *passes)
 {
     if (!batch) return fail(JT_EINVAL, "null batch");
+    const jt::WorkQueue &q = batch->q;
     if (units)
-        for (size_t i = 0; i < batch->units.size(); ++i) {
-            const jt::WorkUnit &w = batch->units[i];
+        for (size_t i = 0; i < q.units.size(); ++i) {
+            const jt::WorkUnit &w = q.units[i];
             const int32_t row[6] = {w.pass, w.line0, w.nlines, w.split, w.wait_pass, w.wait_count};
             std::memcpy(units + 6 * i, row, sizeof(row));
         }
     if (passes) {
-        std::vector<int32_t> nunits(batch->passes.size(), 0);
-        for (const jt::WorkUnit &w : batch->units) nunits[w.pass]++;
-        for (size_t p = 0; p < batch->passes.size(); ++p) {
-            passes[4 * p] = batch->pass_item[p];
-            passes[4 * p + 1] = batch->pass_axis[p];
-            passes[4 * p + 2] = batch->passes[p].lines;
+        std::vector<int32_t> nunits(q.passes.size(), 0);
+        for (const jt::WorkUnit &w : q.units) nunits[w.pass]++;
+        for (size_t p = 0; p < q.passes.size(); ++p) {
+            passes[4 * p] = q.pass_item[p];
+            passes[4 * p + 1] = q.pass_axis[p];
+            passes[4 * p + 2] = q.passes[p].lines;
             passes[4 * p + 3] = nunits[p];
         }
     }
@@ -272,36 +174,24 @@ jt_status jt_batch_tables(jt_batch_t batch, int32_t *units, int32_t *passes)
 jt_status jt_batch_device_bytes(jt_batch_t batch, size_t *bytes)
 {
     if (!batch || !bytes) return fail(JT_EINVAL, "null argument");
-    *bytes = batch->bytes;
+    *bytes = batch->q.bytes;
     return ok();
 }
 
 jt_status jt_batch_bind(jt_batch_t batch, void *dev_buf, size_t bytes, void *stream)
 {
     if (!batch || !dev_buf) return fail(JT_EINVAL, "null argument");
-    if (bytes < batch->bytes) return fail(JT_ENOMEM, "device buffer smaller than jt_batch_device_bytes");
+    if (bytes < batch->q.bytes) return fail(JT_ENOMEM, "device buffer smaller than jt_batch_device_bytes");
     if ((reinterpret_cast<uintptr_t>(dev_buf) & 255u) != 0) return fail(JT_EINVAL, "device buffer not 256-byte aligned");
-    // resolve the factor pointers of every pass inside its plan's bound image
-    for (size_t p = 0; p < batch->passes.size(); ++p) {
-        const jt_plan_t plan = batch->items[batch->pass_item[p]].plan;
-        if (!plan->dev) return fail(JT_ESTATE, "item " + std::to_string(batch->pass_item[p]) + ": plan is not bound");
-        const jt::AxisPlan &ax = plan->ax[batch->pass_axis[p]];
-        const bool f32 = batch->fp32;
-        unsigned char *d = plan->dev;
-        jt::PassDesc &pd = batch->passes[p];
-        pd.tw = d + (f32 ? ax.off_tw32 : ax.off_tw64);
-        pd.bins = reinterpret_cast<const int *>(d + ax.off_bins);
-        pd.binptr = reinterpret_cast<const int *>(d + ax.off_binptr);
-        pd.wv = d + (f32 ? ax.off_wv32 : ax.off_wv64);
-        pd.wvt = d + (f32 ? ax.off_wvt32 : ax.off_wvt64);
-        pd.u = d + (f32 ? ax.off_u32 : ax.off_u64);
-        pd.v = d + (f32 ? ax.off_v32 : ax.off_v64);
+    // the factor pointers of every pass live inside its plan's bound image
+    for (size_t i = 0; i < batch->items.size(); ++i) {
+        if (!batch->plans[i]->dev) return fail(JT_ESTATE, "item " + std::to_string(i) + ": plan is not bound");
+        for (int k = 0; k < batch->items[i].d; ++k) batch->items[i].base[k] = batch->plans[i]->dev;
     }
-    std::vector<unsigned char> img(batch->bytes, 0);
-    std::memcpy(img.data() + batch->off_units, batch->units.data(), batch->units.size() * sizeof(jt::WorkUnit));
-    std::memcpy(img.data() + batch->off_passes, batch->passes.data(), batch->passes.size() * sizeof(jt::PassDesc));
+    jt::resolve_factors(batch->q, batch->items, batch->fp32);
+    std::vector<unsigned char> img = jt::queue_image(batch->q);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    hipError_t e = hipMemcpyAsync(dev_buf, img.data(), batch->bytes, hipMemcpyHostToDevice, s);
+    hipError_t e = hipMemcpyAsync(dev_buf, img.data(), batch->q.bytes, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail(JT_EDEVICE, std::string("batch table copy: ") + hipGetErrorString(e));
     int dev = 0, cus = 0;
@@ -310,7 +200,7 @@ jt_status jt_batch_bind(jt_batch_t batch, void *dev_buf, size_t bytes, void *str
     if (e != hipSuccess || cus <= 0) return fail(JT_EDEVICE, "cannot query the compute-unit count");
     // one block per compute unit: the dynamic LDS (139 KB) admits no second one
     const int want = batch->opt.grid > 0 ? batch->opt.grid : cus;
-    batch->grid = std::max(1, std::min<int>(want, (int)batch->units.size()));
+    batch->grid = std::max(1, std::min<int>(want, (int)batch->q.units.size()));
     batch->dev = static_cast<unsigned char *>(dev_buf);
     return ok();
 }
@@ -318,11 +208,11 @@ jt_status jt_batch_bind(jt_batch_t batch, void *dev_buf, size_t bytes, void *str
 static jt::BatchLaunch launch_args(jt_batch_t batch, const void *in_base, void *out_base)
 {
     jt::BatchLaunch b;
-    b.units = reinterpret_cast<const jt::WorkUnit *>(batch->dev + batch->off_units);
-    b.passes = reinterpret_cast<const jt::PassDesc *>(batch->dev + batch->off_passes);
-    b.counters = reinterpret_cast<uint32_t *>(batch->dev + batch->off_counters);
-    b.nunits = (int32_t)batch->units.size();
-    b.npasses = (int32_t)batch->passes.size();
+    b.units = reinterpret_cast<const jt::WorkUnit *>(batch->dev + batch->q.off_units);
+    b.passes = reinterpret_cast<const jt::PassDesc *>(batch->dev + batch->q.off_passes);
+    b.counters = reinterpret_cast<uint32_t *>(batch->dev + batch->q.off_counters);
+    b.nunits = (int32_t)batch->q.units.size();
+    b.npasses = (int32_t)batch->q.passes.size();
     b.in_base = static_cast<const unsigned char *>(in_base);
     b.out_base = static_cast<unsigned char *>(out_base);
     b.fp32 = batch->fp32 ? 1 : 0;
@@ -384,7 +274,7 @@ jt_status jt_batch_errors(jt_batch_t batch, void *stream, uint32_t *flags)
     if (!batch->dev) return fail(JT_ESTATE, "batch is not bound (jt_batch_bind)");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     uint32_t v = 0;
-    hipError_t e = hipMemcpyAsync(&v, batch->dev + batch->off_counters + sizeof(uint32_t), sizeof(v),
+    hipError_t e = hipMemcpyAsync(&v, batch->dev + batch->q.off_counters + sizeof(uint32_t), sizeof(v),
                                   hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail(JT_EDEVICE, std::string("error word copy: ") + hipGetErrorString(e));

@@ -385,7 +385,6 @@ __device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, 
     const cpx<T> *uf = reinterpret_cast<const cpx<T> *>(a.u);
     const cpx<T> *vf = reinterpret_cast<const cpx<T> *>(a.v);
     const T *wv = reinterpret_cast<const T *>(a.wv);
-    const T *wvt = reinterpret_cast<const T *>(a.wvt);
 
     Twiddles<T, LOG2L> twd[VL];
 #pragma unroll
@@ -420,7 +419,7 @@ __device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, 
     const bool full = JT_FULL_FAST && (n == G::L);  // uniform: the line fills every owned slot
 
     if constexpr (FWD) {
-        // ---- direct block (split group 0): out_j = sum_{k<nu0} WV[k][j] alpha_k
+        // ---- direct block: out_j = sum_{k<nu0} WV[k][j] alpha_k (degrees split over the groups)
 #pragma unroll
         for (int h = 0; h < VL; ++h)
 #pragma unroll
@@ -436,8 +435,8 @@ __device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, 
             for (int h = 0; h < VL; ++h)
 #pragma unroll
                 for (int q = 0; q < 16; ++q) s[h][q] = 0;
-            const int kmax = (sgrp == 0) ? nu0 : 0;
-            for (int k = 0; k < kmax; ++k) {
+            // degrees k = sgrp, sgrp + S, ...: the split groups share the block
+            for (int k = sgrp; k < nu0; k += S) {
                 const T ak = sbuf[k];
 #pragma unroll
                 for (int h = 0; h < VL; ++h)
@@ -455,10 +454,41 @@ __device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, 
                 for (int q = 0; q < 16; ++q) {
                     const int j = pv[h] + G::P * q;
                     T s = 0;
-                    if (sgrp == 0 && j < n)
-                        for (int k = 0; k < nu0; ++k) s += wv[k * n + j] * sbuf[k];
+                    if (j < n)
+                        for (int k = sgrp; k < nu0; k += S) s += wv[k * n + j] * sbuf[k];
                     acc[h][q] = (double)s;
                 }
+        }
+#ifndef JT_HOIST_BINS
+#define JT_HOIST_BINS 1
+#endif
+#ifndef JT_PF_V
+#define JT_PF_V 0
+#endif
+#ifndef JT_PF_U
+#define JT_PF_U 0
+#endif
+        // LDS slots of y[m_j] for the owned nodes (the same for every term);
+        // kept in registers except on the longest lines, which have none to spare
+        constexpr bool kHB = JT_HOIST_BINS && Geo<LOG2L>::BLOCK <= 256;
+        int bix[VL][kHB ? 16 : 1];
+        if constexpr (kHB) {
+#pragma unroll
+            for (int h = 0; h < VL; ++h)
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int j = pv[h] + G::P * q;
+                    bix[h][q] = pad(j < n ? a.bins[j] : 0);
+                }
+        }
+        // factors v_l of the next term, loaded while the current term gathers
+        cpx<T> fv[VL][16];
+        if constexpr (JT_PF_V) {
+            const int l = (sgrp < rank) ? sgrp : rank - 1;
+#pragma unroll
+            for (int h = 0; h < VL; ++h)
+#pragma unroll
+                for (int q = 0; q < 16; ++q) fv[h][q] = vf[l * G::L + pv[h] + G::P * q];
         }
         for (int it = 0; it < iters; ++it) {
             const int l0 = it * S + sgrp;
@@ -469,9 +499,21 @@ __device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, 
             for (int h = 0; h < VL; ++h)
 #pragma unroll
                 for (int q = 0; q < 16; ++q) {
-                    const cpx<T> f = vf[l * G::L + pv[h] + G::P * q];
+                    const cpx<T> f = JT_PF_V ? fv[h][q] : vf[l * G::L + pv[h] + G::P * q];
                     v[h][q] = {f.x * x[h][q], f.y * x[h][q]};
                 }
+            // u_l for the gather, requested before the FFT so that it arrives meanwhile
+            cpx<T> uu[VL][JT_PF_U ? 16 : 1];
+            if constexpr (JT_PF_U) {
+                const cpx<T> *ul = uf + l * n;
+#pragma unroll
+                for (int h = 0; h < VL; ++h)
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) {
+                        const int j = pv[h] + G::P * q;
+                        uu[h][q] = (full || j < n) ? ul[j] : cpx<T>{(T)0, (T)0};
+                    }
+            }
             sync_line<G::TPL>();  // previous users of buf are done
             fft_line<T, LOG2L, VL>(v, buf, pv, twd);
             sync_line<G::TPL>();
@@ -482,6 +524,14 @@ __device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, 
                     const int m = pv[h] + G::P * q;
                     if (m <= G::L / 2) buf[pad(m)] = v[h][q];
                 }
+            if constexpr (JT_PF_V) {
+                const int ln0 = (it + 1) * S + sgrp;
+                const int ln = ln0 < rank ? ln0 : rank - 1;
+#pragma unroll
+                for (int h = 0; h < VL; ++h)
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) fv[h][q] = vf[ln * G::L + pv[h] + G::P * q];
+            }
             sync_line<G::TPL>();
             if (keep) {
                 const cpx<T> *ul = uf + l * n;
@@ -492,8 +542,8 @@ __device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, 
 #pragma unroll
                         for (int q = 0; q < 16; ++q) {
                             const int j = pv[h] + G::P * q;
-                            const cpx<T> y = buf[pad(a.bins[j])];
-                            const cpx<T> u = ul[j];
+                            const cpx<T> y = buf[kHB ? bix[h][q % (kHB ? 16 : 1)] : pad(a.bins[j])];
+                            const cpx<T> u = JT_PF_U ? uu[h][q % (JT_PF_U ? 16 : 1)] : ul[j];
                             acc[h][q] += (double)(u.x * y.x - u.y * y.y);
                         }
                 } else {
@@ -503,8 +553,8 @@ __device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, 
                         for (int q = 0; q < 16; ++q) {
                             const int j = pv[h] + G::P * q;
                             if (j < n) {
-                                const cpx<T> y = buf[pad(a.bins[j])];
-                                const cpx<T> u = ul[j];
+                                const cpx<T> y = buf[kHB ? bix[h][q % (kHB ? 16 : 1)] : pad(a.bins[j])];
+                                const cpx<T> u = JT_PF_U ? uu[h][q % (JT_PF_U ? 16 : 1)] : ul[j];
                                 acc[h][q] += (double)(u.x * y.x - u.y * y.y);
                             }
                         }
@@ -512,21 +562,28 @@ __device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, 
             }
         }
     } else {
-        // ---- direct block (split group 0): alpha_k = sum_j WV[k][j] g_j for
-        // k < nu0.  Every lane sums over its own nodes for a chunk of KC
-        // degrees (coalesced rows of WV), the partial sums are added across
-        // the line's lanes, and the lane that owns degree k keeps the total.
+        // ---- direct block: alpha_k = sum_j WV[k][j] g_j for k < nu0.  The
+        // degrees go in chunks of KC, chunk c to split group c mod S.  Every
+        // lane sums over its own nodes (coalesced rows of WV), the partial sums
+        // are added across the line's lanes, and the totals wait in the
+        // group's line buffer until the lanes that own those degrees pick them
+        // up.  All groups run the same number of rounds (line_sum may hold a
+        // block barrier).
 #pragma unroll
         for (int h = 0; h < VL; ++h)
 #pragma unroll
             for (int q = 0; q < 16; ++q) acc[h][q] = 0.0;
-        constexpr int KC = 8;
+        constexpr int KC = Geo<LOG2L>::BLOCK <= 256 ? 8 : 2;  // fewer live sums on register-poor long lines
         double *red = reinterpret_cast<double *>(buf);  // free until the first term
-        for (int k0 = 0; k0 < nu0; k0 += KC) {
+        const int nchunks = (nu0 + KC - 1) / KC;
+        const int rounds = (nchunks + S - 1) / S;
+        for (int rd = 0; rd < rounds; ++rd) {
+            const int ch = rd * S + sgrp;
+            const int k0 = ch * KC;
             double part[KC];
 #pragma unroll
             for (int c = 0; c < KC; ++c) part[c] = 0.0;
-            if (sgrp == 0) {
+            if (ch < nchunks) {
 #pragma unroll
                 for (int h = 0; h < VL; ++h)
 #pragma unroll
@@ -540,17 +597,40 @@ __device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, 
                         }
                     }
             }
-            line_sum<G::TPL, KC>(part, red, tid % G::TPL);
+            line_sum<G::TPL, KC>(part, red + 64, tid % G::TPL);
+            if (ch < nchunks && tid % G::TPL == 0)
 #pragma unroll
-            for (int c = 0; c < KC; ++c) {
-                const int k = k0 + c;
-#pragma unroll
-                for (int h = 0; h < VL; ++h)
-#pragma unroll
-                    for (int q = 0; q < 16; ++q)
-                        if (k < nu0 && k == pv[h] + G::P * q) acc[h][q] = part[c];
-            }
+                for (int c = 0; c < KC; ++c)
+                    if (k0 + c < nu0) red[k0 + c] = part[c];
         }
+        sync_line<G::TPL>();
+#pragma unroll
+        for (int h = 0; h < VL; ++h)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int k = pv[h] + G::P * q;
+                if (k < nu0 && (k / KC) % S == sgrp) acc[h][q] = red[k];
+            }
+        // the nodes of each owned bin m (at most two in almost every plan), as
+        // padded LDS slots packed j_a | j_b << 16 (0xffff: none); the same for
+        // every term, so they are read once
+        constexpr bool kBP = Geo<LOG2L>::BLOCK <= 256;
+        const bool two = kBP && a.max_per_bin <= 2;
+        unsigned bpair[VL][kBP ? 16 : 1];
+#pragma unroll
+        for (int h = 0; h < VL; ++h)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int m = pv[h] + G::P * q;
+                unsigned w = 0xffffffffu;
+                if (two && m <= G::L / 2) {
+                    const int j0 = a.binptr[m], j1 = a.binptr[m + 1];
+                    const unsigned ja = (j1 > j0) ? (unsigned)pad(j0) : 0xffffu;
+                    const unsigned jb = (j1 > j0 + 1) ? (unsigned)pad(j0 + 1) : 0xffffu;
+                    w = ja | (jb << 16);
+                }
+                bpair[h][q % (kBP ? 16 : 1)] = w;
+            }
         for (int it = 0; it < iters; ++it) {
             const int l0 = it * S + sgrp;
             const bool keep = l0 < rank;
@@ -579,18 +659,32 @@ __device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, 
             }
             sync_line<G::TPL>();
             cpx<T> v[VL][16];
+            if (two) {
 #pragma unroll
-            for (int h = 0; h < VL; ++h)
+                for (int h = 0; h < VL; ++h)
 #pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    const int m = pv[h] + G::P * q;
-                    cpx<T> z = {(T)0, (T)0};
-                    if (m <= G::L / 2) {
-                        const int j0 = a.binptr[m], j1 = a.binptr[m + 1];
-                        for (int jj = j0; jj < j1; ++jj) z = z + buf[pad(jj)];
+                    for (int q = 0; q < 16; ++q) {
+                        const unsigned w = bpair[h][q % (kBP ? 16 : 1)];
+                        const unsigned ja = w & 0xffffu, jb = w >> 16;
+                        cpx<T> z = {(T)0, (T)0};
+                        if (ja != 0xffffu) z = buf[ja];
+                        if (jb != 0xffffu) z = z + buf[jb];
+                        v[h][q] = z;
                     }
-                    v[h][q] = z;
-                }
+            } else {
+#pragma unroll
+                for (int h = 0; h < VL; ++h)
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) {
+                        const int m = pv[h] + G::P * q;
+                        cpx<T> z = {(T)0, (T)0};
+                        if (m <= G::L / 2) {
+                            const int j0 = a.binptr[m], j1 = a.binptr[m + 1];
+                            for (int jj = j0; jj < j1; ++jj) z = z + buf[pad(jj)];
+                        }
+                        v[h][q] = z;
+                    }
+            }
             sync_line<G::TPL>();
             fft_line<T, LOG2L, VL>(v, buf, pv, twd);
             if (keep) {

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "plan.h"
+#include "queue.h"
 
 struct jt_plan_s {
     int d = 0;
@@ -43,6 +44,8 @@ jt_status guarded(F f)
         return f();
     } catch (const std::invalid_argument &e) {
         return fail(JT_EINVAL, e.what());
+    } catch (const unsupported &e) {
+        return fail(JT_EUNSUPPORTED, e.what());
     } catch (const std::bad_alloc &) {
         return fail(JT_ENOMEM, "host allocation failed");
     } catch (const std::runtime_error &e) {

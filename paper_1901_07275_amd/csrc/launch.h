@@ -25,7 +25,6 @@ struct AxisLaunch {
     const int *bins = nullptr;   // n
     const int *binptr = nullptr; // L/2 + 2
     const void *wv = nullptr;    // nu0 x n   (WV[k*n + j])
-    const void *wvt = nullptr;   // n x nu0   (WV^T[j*nu0 + k])
     const void *u = nullptr;     // rank x n complex
     const void *v = nullptr;     // rank x L complex
 };

@@ -759,22 +759,29 @@ void exact_entries(const AxisPlan &ax, int count, const int *rows, const int *de
 // ------------------------------------------------------------------ packing
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-size_t layout_axis(AxisPlan &ax, size_t base)
+size_t layout_axis(AxisPlan &ax, size_t base, int precs)
 {
     size_t o = align256(base);
     const size_t n = ax.n, L = ax.L, r = ax.rank, nu = ax.nu0;
-    ax.off_tw64 = o;   o = align256(o + L * 16);
-    ax.off_tw32 = o;   o = align256(o + L * 8);
-    ax.off_bins = o;   o = align256(o + n * 4);
-    ax.off_binptr = o; o = align256(o + (L / 2 + 2) * 4);
-    ax.off_wv64 = o;   o = align256(o + nu * n * 8);
-    ax.off_wv32 = o;   o = align256(o + nu * n * 4);
-    ax.off_wvt64 = o;  o = align256(o + nu * n * 8);
-    ax.off_wvt32 = o;  o = align256(o + nu * n * 4);
-    ax.off_u64 = o;    o = align256(o + r * n * 16);
-    ax.off_u32 = o;    o = align256(o + r * n * 8);
-    ax.off_v64 = o;    o = align256(o + r * L * 16);
-    ax.off_v32 = o;    o = align256(o + r * L * 8);
+    const bool f64 = precs & kPackF64, f32 = precs & kPackF32;
+    auto sec = [&](size_t &off, bool present, size_t bytes) {
+        if (!present) {
+            off = kAbsent;
+            return;
+        }
+        off = o;
+        o = align256(o + bytes);
+    };
+    sec(ax.off_tw64, f64, L * 16);
+    sec(ax.off_tw32, f32, L * 8);
+    sec(ax.off_bins, true, n * 4);
+    sec(ax.off_binptr, true, (L / 2 + 2) * 4);
+    sec(ax.off_wv64, f64, nu * n * 8);
+    sec(ax.off_wv32, f32, nu * n * 4);
+    sec(ax.off_u64, f64, r * n * 16);
+    sec(ax.off_u32, f32, r * n * 8);
+    sec(ax.off_v64, f64, r * L * 16);
+    sec(ax.off_v32, f32, r * L * 8);
     ax.bytes = o - base;
     return o;
 }
@@ -782,40 +789,46 @@ size_t layout_axis(AxisPlan &ax, size_t base)
 void pack_axis(const AxisPlan &ax, unsigned char *blob)
 {
     const int n = ax.n, L = ax.L, r = ax.rank, nu = ax.nu0;
-    double *tw64 = (double *)(blob + ax.off_tw64);
-    float *tw32 = (float *)(blob + ax.off_tw32);
+    const bool f64 = ax.off_tw64 != kAbsent, f32 = ax.off_tw32 != kAbsent;
     for (int p = 0; p < L; ++p) {
         // DFT twiddles of eq. (47): exp(+2 pi i p / L)
         ld ang = 2 * kPi * p / L;
         ld c = cosl(ang), s = sinl(ang);
-        tw64[2 * p] = (double)c; tw64[2 * p + 1] = (double)s;
-        tw32[2 * p] = (float)c; tw32[2 * p + 1] = (float)s;
+        if (f64) {
+            double *tw64 = (double *)(blob + ax.off_tw64);
+            tw64[2 * p] = (double)c; tw64[2 * p + 1] = (double)s;
+        }
+        if (f32) {
+            float *tw32 = (float *)(blob + ax.off_tw32);
+            tw32[2 * p] = (float)c; tw32[2 * p + 1] = (float)s;
+        }
     }
     std::memcpy(blob + ax.off_bins, ax.bins.data(), (size_t)n * 4);
     int32_t *bp = (int32_t *)(blob + ax.off_binptr);
     for (int m = 0; m < L / 2 + 2; ++m) bp[m] = (m < (int)ax.binptr.size()) ? ax.binptr[m] : n;
-    double *wv64 = (double *)(blob + ax.off_wv64);
-    float *wv32 = (float *)(blob + ax.off_wv32);
-    for (size_t i = 0; i < (size_t)nu * n; ++i) { wv64[i] = ax.WV[i]; wv32[i] = (float)ax.WV[i]; }
-    double *wvt64 = (double *)(blob + ax.off_wvt64);
-    float *wvt32 = (float *)(blob + ax.off_wvt32);
-    for (int k = 0; k < nu; ++k)
-        for (int j = 0; j < n; ++j) {
-            double w = ax.WV[(size_t)k * n + j];
-            wvt64[(size_t)j * nu + k] = w;
-            wvt32[(size_t)j * nu + k] = (float)w;
-        }
-    double *u64 = (double *)(blob + ax.off_u64);
-    float *u32 = (float *)(blob + ax.off_u32);
-    for (size_t i = 0; i < (size_t)r * n; ++i) {
-        u64[2 * i] = ax.U[i].real(); u64[2 * i + 1] = ax.U[i].imag();
-        u32[2 * i] = (float)ax.U[i].real(); u32[2 * i + 1] = (float)ax.U[i].imag();
+    for (size_t i = 0; i < (size_t)nu * n; ++i) {
+        if (f64) ((double *)(blob + ax.off_wv64))[i] = ax.WV[i];
+        if (f32) ((float *)(blob + ax.off_wv32))[i] = (float)ax.WV[i];
     }
-    double *v64 = (double *)(blob + ax.off_v64);
-    float *v32 = (float *)(blob + ax.off_v32);
+    for (size_t i = 0; i < (size_t)r * n; ++i) {
+        if (f64) {
+            double *u64 = (double *)(blob + ax.off_u64);
+            u64[2 * i] = ax.U[i].real(); u64[2 * i + 1] = ax.U[i].imag();
+        }
+        if (f32) {
+            float *u32 = (float *)(blob + ax.off_u32);
+            u32[2 * i] = (float)ax.U[i].real(); u32[2 * i + 1] = (float)ax.U[i].imag();
+        }
+    }
     for (size_t i = 0; i < (size_t)r * L; ++i) {
-        v64[2 * i] = ax.V[i].real(); v64[2 * i + 1] = ax.V[i].imag();
-        v32[2 * i] = (float)ax.V[i].real(); v32[2 * i + 1] = (float)ax.V[i].imag();
+        if (f64) {
+            double *v64 = (double *)(blob + ax.off_v64);
+            v64[2 * i] = ax.V[i].real(); v64[2 * i + 1] = ax.V[i].imag();
+        }
+        if (f32) {
+            float *v32 = (float *)(blob + ax.off_v32);
+            v32[2 * i] = (float)ax.V[i].real(); v32[2 * i + 1] = (float)ax.V[i].imag();
+        }
     }
 }
 

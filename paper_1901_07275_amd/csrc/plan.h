@@ -40,7 +40,7 @@ struct AxisPlan {
     int rsvd_rounds = 0;
     // offsets of this axis' sections inside the device blob (bytes)
     size_t off_tw64 = 0, off_tw32 = 0, off_bins = 0, off_binptr = 0;
-    size_t off_wv64 = 0, off_wv32 = 0, off_wvt64 = 0, off_wvt32 = 0, off_u64 = 0, off_u32 = 0, off_v64 = 0, off_v32 = 0;
+    size_t off_wv64 = 0, off_wv32 = 0, off_u64 = 0, off_u32 = 0, off_v64 = 0, off_v32 = 0;
     size_t bytes = 0;
 };
 
@@ -59,9 +59,14 @@ void build_axis(AxisPlan &ax, int n, double a, double b, double tol, const PlanO
 // (row j, degree k) pairs, k in [nu0, n).  For diagnostics and tests.
 void exact_entries(const AxisPlan &ax, int count, const int *rows, const int *degs, cd *out);
 
-// Serialise the device sections of one axis into `dst` (size ax.bytes).
+// Device image of one axis.  layout_axis places the sections at 256-byte
+// aligned offsets from `base` (returns the end); precs selects the fp64 and/or
+// fp32 copies of the factors (absent sections get offset kAbsent).  pack_axis
+// writes the sections into the image starting at dst (offsets count from dst).
+constexpr int kPackF64 = 1, kPackF32 = 2;
+constexpr size_t kAbsent = ~(size_t)0;
+size_t layout_axis(AxisPlan &ax, size_t base, int precs = kPackF64 | kPackF32);
 void pack_axis(const AxisPlan &ax, unsigned char *dst);
-size_t layout_axis(AxisPlan &ax, size_t base);
 
 // Gauss-Jacobi nodes/weights on their own (ascending t), as used by the plan.
 void gauss_jacobi(int n, double a, double b, std::vector<double> &t, std::vector<double> &x,

@@ -24,11 +24,11 @@ def test_every_declared_symbol_is_exported():
     assert len(names) >= 27
     for name in names:
         assert hasattr(lib, name), name
-    assert set(jt.SYMBOLS) | {"jt_last_error", "jt_version"} >= set(names)
+    assert set(jt.SYMBOLS) | {"jt_last_error", "jt_version", "jt_clock"} >= set(names)
 
 
 def test_version():
-    assert jt.version() == 110
+    assert jt.version() == 120
 
 
 @pytest.mark.parametrize("n,ab,tol", [

@@ -70,3 +70,37 @@ def batch_2d(count: int, seed: int = 1041, nmin: int = 32, nmax: int = 512):
         n = (log_uniform_int(rng, nmin, nmax), log_uniform_int(rng, nmin, nmax))
         items.append((n, random_params(rng, 2), rng.standard_normal(n)))
     return items
+
+
+def serving_pairs(seed: int = 105, count: int = 16):
+    """The (a, b) pairs a serving stream draws from: `count` pairs drawn once,
+    each entry uniform in (-0.5, 0.5)."""
+    rng = np.random.default_rng(seed)
+    return [(float(rng.uniform(-0.5, 0.5)), float(rng.uniform(-0.5, 0.5))) for _ in range(count)]
+
+
+def serving_stream(count: int, seed: int = 105):
+    """Request descriptors of the mixed serving stream: per request
+    (d, shape, params, direction) with d = 1, 2, 3 at probabilities
+    0.4 / 0.4 / 0.2; each axis's n log-uniform in [64, 4096] (1D), [64, 1024]
+    (2D) or [32, 256] (3D); (a, b) per axis from the 16 serving pairs;
+    forward or inverse with probability 1/2 each (0 = forward, 1 = inverse).
+    Inputs are drawn separately (i.i.d. N(0, 1))."""
+    pairs = serving_pairs(seed)
+    rng = np.random.default_rng(seed + 1)
+    ranges = {1: (64, 4096), 2: (64, 1024), 3: (32, 256)}
+    out = []
+    for _ in range(count):
+        d = int(rng.choice([1, 2, 3], p=[0.4, 0.4, 0.2]))
+        lo, hi = ranges[d]
+        shape = tuple(log_uniform_int(rng, lo, hi) for _ in range(d))
+        params = tuple(pairs[int(rng.integers(0, len(pairs)))] for _ in range(d))
+        direction = int(rng.integers(0, 2))
+        out.append((d, shape, params, direction))
+    return out
+
+
+def poisson_arrivals(count: int, rate: float, seed: int = 106) -> np.ndarray:
+    """Arrival times (seconds from 0) of a Poisson process with the given rate."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=count))
