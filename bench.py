@@ -44,17 +44,24 @@ def axis_flops(n: int, L: int, nu0: int, rank: int, lines: int) -> float:
     return per_line * lines
 
 
+def kernel_source_hash() -> str:
+    """sha256[:16] over the sources the axis-pass kernel is built from."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in ("axis_pass.hip", "fft_line.h", "launch.h"):
+        h.update(open(os.path.join(ROOT, "paper_1901_07275_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def measured_traffic(kernel_prefix: str):
     """HBM bytes per launch of the given kernel family from the committed
     rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when the kernel source
     changed after the counters were taken."""
-    import hashlib
-
     prof = os.path.join(ROOT, "profiles", "axis_pass_2d_n1024_traffic.json")
-    src = os.path.join(ROOT, "paper_1901_07275_amd", "csrc", "axis_pass.hip")
     try:
         rec = json.load(open(prof))
-        h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        h = kernel_source_hash()
     except (OSError, ValueError):
         return None
     if rec.get("source_sha256_16") != h:

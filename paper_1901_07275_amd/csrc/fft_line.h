@@ -470,7 +470,10 @@ __device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, 
 #endif
         // LDS slots of y[m_j] for the owned nodes (the same for every term);
         // kept in registers except on the longest lines, which have none to spare
-        constexpr bool kHB = JT_HOIST_BINS && Geo<LOG2L>::BLOCK <= 256;
+#ifndef JT_HOIST_F64
+#define JT_HOIST_F64 1
+#endif
+        constexpr bool kHB = JT_HOIST_BINS && Geo<LOG2L>::BLOCK <= 256 && (sizeof(T) == 4 || JT_HOIST_F64);
         int bix[VL][kHB ? 16 : 1];
         if constexpr (kHB) {
 #pragma unroll
@@ -614,7 +617,10 @@ __device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, 
         // the nodes of each owned bin m (at most two in almost every plan), as
         // padded LDS slots packed j_a | j_b << 16 (0xffff: none); the same for
         // every term, so they are read once
-        constexpr bool kBP = Geo<LOG2L>::BLOCK <= 256;
+#ifndef JT_BPAIR_F64
+#define JT_BPAIR_F64 0
+#endif
+        constexpr bool kBP = Geo<LOG2L>::BLOCK <= 256 && (sizeof(T) == 4 || JT_BPAIR_F64);
         const bool two = kBP && a.max_per_bin <= 2;
         unsigned bpair[VL][kBP ? 16 : 1];
 #pragma unroll
