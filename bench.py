@@ -136,16 +136,22 @@ def batched(args) -> int:
         shapes = [n for n, _, _ in items]
         abs_ = [ab for _, ab, _ in items]
     xs = [x for _, _, x in items]
+    from paper_1901_07275_amd import autotune
+
+    tuning = autotune.load()
+    # the tuned FFT-versus-dense crossover: 1D items are single lines, 2D items many
+    db = [autotune.dense_below(1 if len(s) == 1 else min(s), jt.PREC_FP32_BULK, tuning) for s in shapes]
     print("planning %d items" % len(items), file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    plans = jt.plan_many(shapes, abs_, 1e-7)
+    plans = jt.plan_many(shapes, abs_, 1e-7, dense_below=db)
     t_plan = time.perf_counter() - t0
     print("planned in %.1f s" % t_plan, file=sys.stderr, flush=True)
     arena = jt.PlanArena(plans, dev)
     sizes = [int(np.prod(s)) for s in shapes]
     offs = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(int)
     coeffs = int(sum(sizes))
-    B = jt.Batch(plans, [jt.FORWARD] * len(plans), offs, offs, jt.F32, jt.F32, jt.PREC_FP32_BULK).bind(dev)
+    B = jt.Batch(plans, [jt.FORWARD] * len(plans), offs, offs, jt.F32, jt.F32, jt.PREC_FP32_BULK,
+                 max_split=int(tuning.get("max_split", 0))).bind(dev)
     inp = torch.from_numpy(np.concatenate([x.ravel() for x in xs])).to(dev, torch.float32)
     out = torch.empty_like(inp)
     stream = torch.cuda.current_stream(dev)
@@ -210,7 +216,8 @@ def batched(args) -> int:
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": args.workload, "items": len(items), "coeffs": coeffs, "tol": 1e-7,
                    "units": info["units"], "grid": info["grid"], "threads": info["threads"],
-                   "plan_seconds": t_plan, "graph": True},
+                   "plan_seconds": t_plan, "graph": True, "tuning": tuning.get("source"),
+                   "dense_items": int(sum(1 for p in plans if p.info(0)["nu0"] == p.info(0)["n"]))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
                      "frac": achieved / 8000.0, "traffic": None, "kernel": "batch_kernel<float>",
                      "bytes_per_launch": nbytes},
@@ -326,7 +333,10 @@ def serving(args) -> int:
     data = np.random.default_rng(107).standard_normal(1 << 25).astype(np.float32)
     pool = PinnedPool(torch, 1 << 29)  # 2 GiB of pinned host buffers
     arena = 16 << 30
-    S = jt.Server(arena, tol=1e-7, prec=jt.PREC_FP32_BULK, dtype=jt.F32)
+    from paper_1901_07275_amd import autotune
+
+    S = jt.Server(arena, tol=1e-7, prec=jt.PREC_FP32_BULK, dtype=jt.F32,
+                  dense_below=autotune.dense_below(64, jt.PREC_FP32_BULK))
     print("warm-up %d requests" % len(warm), file=sys.stderr, flush=True)
     serve_stream(jt, S, warm, data, None, pool)
     # first pass over the measured requests, all offered at once: their plans

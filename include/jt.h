@@ -68,7 +68,8 @@ typedef enum { JT_FORWARD = 0, JT_INVERSE = 1 } jt_direction;
 /* Optional planning knobs; jt_plan() uses the defaults listed here. */
 typedef struct {
     int nu0;          /* width of the direct (low-degree) block; default 27 (Section 3.1) */
-    int dense_below;  /* n below this uses the direct block for all degrees; default 64 */
+    int dense_below;  /* n below this (and at most 1024) keeps the whole matrix: the dense
+                         matrix-core pass, no FFT terms; default 64 */
     int oversample;   /* q of Algorithm 2.1; default 2 */
     int iterations;   /* repetitions of steps 2-3 of Algorithm 2.1; default 2 (Section 2.1) */
     uint64_t seed;    /* 0: derived from (n, a, b, tol), so plans are reproducible */
@@ -231,8 +232,10 @@ jt_status jt_batch_create(int count, const jt_plan_t *plans, const int *dirs, co
                           const jt_batch_options *opt, jt_batch_t *batch);
 jt_status jt_batch_destroy(jt_batch_t batch);
 jt_status jt_batch_info_get(jt_batch_t batch, jt_batch_info *info);
-/* Host copy of the unit table in queue order: 6 int32 per unit
- * (pass, first line, lines, split S, pass waited for or -1, units waited for),
+/* Host copy of the unit table in queue order: 7 int32 per unit
+ * (pass, first line, lines, split S, pass waited for or -1, units waited for,
+ * passes run whole: > 0 for a small multi-axis item done inside one block,
+ * whose row then covers passes pass .. pass + npass - 1 and every line),
  * and of the pass table: 4 int32 per pass (item, axis, lines, units).
  * Either pointer may be NULL. */
 jt_status jt_batch_tables(jt_batch_t batch, int32_t *units, int32_t *passes);
@@ -274,6 +277,7 @@ typedef struct {
     int max_inflight;        /* launches in flight; 0 = 2 */
     int plan_threads;        /* host planning threads; 0 = hardware threads (at most 16) */
     jt_batch_options batch;  /* unit shaping of each launch */
+    int dense_below;         /* axes shorter than this use the dense matrix-core pass; 0 = 64 */
 } jt_server_options;
 
 typedef struct {

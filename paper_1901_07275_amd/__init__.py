@@ -73,7 +73,7 @@ class BatchInfo(ctypes.Structure):
 class ServerOptions(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("prec", ctypes.c_int), ("in_dtype", ctypes.c_int),
                 ("out_dtype", ctypes.c_int), ("max_batch", ctypes.c_int), ("max_inflight", ctypes.c_int),
-                ("plan_threads", ctypes.c_int), ("batch", BatchOptions)]
+                ("plan_threads", ctypes.c_int), ("batch", BatchOptions), ("dense_below", ctypes.c_int)]
 
 
 class RequestInfo(ctypes.Structure):
@@ -414,9 +414,9 @@ class Batch:
         return {f: getattr(inf, f) for f, _ in BatchInfo._fields_}
 
     def tables(self):
-        """(units: (U, 6) int32 in queue order, passes: (P, 4) int32)."""
+        """(units: (U, 7) int32 in queue order, passes: (P, 4) int32)."""
         inf = self.info()
-        u = np.empty((inf["units"], 6), dtype=np.int32)
+        u = np.empty((inf["units"], 7), dtype=np.int32)
         p = np.empty((inf["passes"], 4), dtype=np.int32)
         _check(_lib.jt_batch_tables(self._h, u.ctypes.data_as(_i32p), p.ctypes.data_as(_i32p)))
         return u, p
@@ -493,7 +493,7 @@ class Server:
 
     def __init__(self, arena_bytes: int, tol: float = 1e-7, prec: int = PREC_FP32_BULK, dtype: int = F32,
                  max_batch: int = 0, max_inflight: int = 0, plan_threads: int = 0, device=None,
-                 max_split: int = 0, min_units: int = 0, grid: int = 0):
+                 max_split: int = 0, min_units: int = 0, grid: int = 0, dense_below: int = 0):
         import torch
 
         device = torch.device(device or "cuda")
@@ -501,7 +501,8 @@ class Server:
         base = self._arena.data_ptr() + (-self._arena.data_ptr()) % 256
         torch.cuda.synchronize(device)
         opt = ServerOptions(float(tol), int(prec), int(dtype), int(dtype), int(max_batch), int(max_inflight),
-                            int(plan_threads), BatchOptions(int(max_split), int(min_units), int(grid)))
+                            int(plan_threads), BatchOptions(int(max_split), int(min_units), int(grid)),
+                            int(dense_below))
         h = _vp()
         _check(_lib.jt_server_create(_vp(base), int(arena_bytes), ctypes.byref(opt), ctypes.byref(h)))
         self._h = h

@@ -26,6 +26,7 @@
 
 #include "launch.h"
 
+#include "dense_pass.h"
 #include "fft_line.h"
 
 namespace jt {
@@ -63,6 +64,39 @@ __global__ void __launch_bounds__(Geo<LOG2L>::BLOCK == 64 ? 256 : Geo<LOG2L>::BL
                               (int)threadIdx.x % G::BLOCK, smem, tw);
 }
 
+// Dense pass (every degree in the direct block): 16 lines per block of four
+// waves, on the matrix cores.
+template <class T, int FWD>
+__global__ void __launch_bounds__(256) dense_pass(AxisLaunch a)
+{
+    extern __shared__ unsigned char lds_raw[];
+    const unsigned line0 = blockIdx.x * (unsigned)kDenseLines;
+    const unsigned end = line0 + kDenseLines < (unsigned)a.lines ? line0 + kDenseLines : (unsigned)a.lines;
+    dense_lines<T, FWD>(a, line0, end, reinterpret_cast<T *>(lds_raw));
+}
+
+template <class T>
+hipError_t launch_dense(const AxisLaunch &a, hipStream_t s)
+{
+    const long long blocks = (a.lines + kDenseLines - 1) / kDenseLines;
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    const size_t lds = dense_lds_bytes(a.n, sizeof(T) == 4);
+    static bool attr_set[2] = {false, false};
+    if (!attr_set[a.forward ? 1 : 0]) {
+        const void *fn = a.forward ? reinterpret_cast<const void *>(&dense_pass<T, 1>)
+                                   : reinterpret_cast<const void *>(&dense_pass<T, 0>);
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        (void)hipGetLastError();
+        attr_set[a.forward ? 1 : 0] = true;
+    }
+    if (a.forward)
+        hipLaunchKernelGGL((dense_pass<T, 1>), dim3((unsigned)blocks), dim3(256), lds, s, a);
+    else
+        hipLaunchKernelGGL((dense_pass<T, 0>), dim3((unsigned)blocks), dim3(256), lds, s, a);
+    return hipGetLastError();
+}
+
 template <class T, int LOG2L>
 hipError_t launch_t(const AxisLaunch &a, hipStream_t s)
 {
@@ -98,6 +132,10 @@ hipError_t launch_t(const AxisLaunch &a, hipStream_t s)
 template <class T>
 hipError_t launch_prec(const AxisLaunch &a, hipStream_t s)
 {
+    if (a.nu0 == a.n) {
+        if (a.n > kDenseMax) return hipErrorInvalidValue;
+        return launch_dense<T>(a, s);
+    }
     switch (a.L) {
     case 64: return launch_t<T, 6>(a, s);
     case 128: return launch_t<T, 7>(a, s);

@@ -2,7 +2,8 @@
 // transforms of uneven size, dimension and (a, b) in one launch.
 //
 // Every axis pass of every item becomes one PassDesc; every pass is cut into
-// work units of a few lines.  The units sit in a device table in queue order;
+// work units of a few lines (a small multi-axis item instead becomes a single
+// unit that runs all its passes in order inside one block).  The units sit in a device table in queue order;
 // the blocks of one persistent grid take them one at a time from an atomic
 // head counter.  A unit of a later axis pass of an item waits until every unit
 // of that item's previous pass has been counted done (the passes of one item
@@ -27,7 +28,8 @@ struct PassDesc {
     int32_t lines = 0, stride = 1;
     int32_t n = 0, L = 0, nu0 = 0, rank = 0, max_per_bin = 0;
     int32_t forward = 1;
-    int32_t pad_ = 0;
+    int32_t publish = 0;      // a later pass of the item waits for this one (cross-block)
+    int32_t split = 1, cap = 1;  // rank split and lines per chunk of this pass
     // factor sections of the item's bound plan (device pointers)
     const void *tw = nullptr;
     const int *bins = nullptr;
@@ -45,6 +47,8 @@ struct WorkUnit {
     int32_t split = 1;       // S: split groups sharing each line (rank terms divided among them)
     int32_t wait_pass = -1;  // pass that must be complete first (-1: none)
     int32_t wait_count = 0;  // number of units of wait_pass
+    int32_t npass = 0;       // > 0: a whole small item, passes pass .. pass + npass - 1, every line,
+                             // in order inside the block (no cross-block waits)
 };
 
 // Status bits the kernel can raise in the error word.
@@ -78,6 +82,12 @@ inline int group_threads(int L)
     return tpl < 64 ? 64 : tpl;
 }
 inline int group_lines(int L) { return group_threads(L) / ((L / 16) / lanes_per_thread(L)); }
+// Multi-axis items with at most this many elements per axis pass, summed over
+// the passes, run whole inside one block.
+constexpr long long kFuseMaxElems = 1LL << 19;
+// Dense (matrix-core) units: lines per unit and the longest dense line.
+constexpr int kDenseLinesPerUnit = 16;
+constexpr int kDenseMaxLine = 1024;
 
 // Zero the counters and launch the persistent kernel on `stream`.
 hipError_t launch_batch(const BatchLaunch &b, hipStream_t stream);

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include "batch.h"
+#include "dense_pass.h"
 #include "fft_line.h"
 
 namespace jt {
@@ -36,6 +37,44 @@ __device__ void wait_done(const uint32_t *ctr, uint32_t need, uint32_t *err)
 
 // One variant per length, kept out of line: inlined together, the nine
 // variants of both directions would share one register allocation and spill.
+__device__ __forceinline__ AxisLaunch launch_of(const PassDesc &d, const BatchLaunch &b, bool fp32)
+{
+    AxisLaunch a;
+    a.in = (d.in_from_out ? (const unsigned char *)b.out_base : b.in_base) + d.in_off;
+    a.out = b.out_base + d.out_off;
+    a.in_f64 = d.in_f64;
+    a.out_f64 = d.out_f64;
+    a.lines = d.lines;
+    a.stride = d.stride;
+    a.n = d.n;
+    a.L = d.L;
+    a.nu0 = d.nu0;
+    a.rank = d.rank;
+    a.max_per_bin = d.max_per_bin;
+    a.forward = d.forward;
+    a.fp32 = fp32;
+    a.tw = d.tw;
+    a.bins = d.bins;
+    a.binptr = d.binptr;
+    a.wv = d.wv;
+    a.u = d.u;
+    a.v = d.v;
+    return a;
+}
+
+// A dense unit: 16 lines on the matrix cores (every degree in the direct block).
+template <class T>
+__device__ __attribute__((noinline)) void run_dense(const PassDesc &d, const WorkUnit &w, const BatchLaunch &b,
+                                                    cpx<T> *smem)
+{
+    const AxisLaunch a = launch_of(d, b, sizeof(T) == 4);
+    const unsigned end = (unsigned)(w.line0 + w.nlines);
+    if (d.forward)
+        dense_lines<T, 1>(a, (unsigned)w.line0, end, reinterpret_cast<T *>(smem));
+    else
+        dense_lines<T, 0>(a, (unsigned)w.line0, end, reinterpret_cast<T *>(smem));
+}
+
 template <class T, int LOG2L>
 __device__ __attribute__((noinline)) void run_unit(const PassDesc &d, const WorkUnit &w, const BatchLaunch &b, cpx<T> *smem)
 {
@@ -45,26 +84,7 @@ __device__ __attribute__((noinline)) void run_unit(const PassDesc &d, const Work
     if constexpr (sizeof(T) == 8 && LOG2L > 13) {
         return;  // rejected on the host (the line buffer would not fit in LDS)
     } else {
-        AxisLaunch a;
-        a.in = (d.in_from_out ? (const unsigned char *)b.out_base : b.in_base) + d.in_off;
-        a.out = b.out_base + d.out_off;
-        a.in_f64 = d.in_f64;
-        a.out_f64 = d.out_f64;
-        a.lines = d.lines;
-        a.stride = d.stride;
-        a.n = d.n;
-        a.L = d.L;
-        a.nu0 = d.nu0;
-        a.rank = d.rank;
-        a.max_per_bin = d.max_per_bin;
-        a.forward = d.forward;
-        a.fp32 = sizeof(T) == 4;
-        a.tw = d.tw;
-        a.bins = d.bins;
-        a.binptr = d.binptr;
-        a.wv = d.wv;
-        a.u = d.u;
-        a.v = d.v;
+        const AxisLaunch a = launch_of(d, b, sizeof(T) == 4);
         const int S = w.split;
         const int grp = (int)threadIdx.x / G::BLOCK;
         const int vb = grp / S, sgrp = grp % S;
@@ -76,6 +96,31 @@ __device__ __attribute__((noinline)) void run_unit(const PassDesc &d, const Work
             pass_lines<T, LOG2L, 1, VL>(a, line0, line_end, S, sgrp, (int)threadIdx.x % G::BLOCK, vs, tw);
         else
             pass_lines<T, LOG2L, 0, VL>(a, line0, line_end, S, sgrp, (int)threadIdx.x % G::BLOCK, vs, tw);
+    }
+}
+
+// One chunk of lines of one pass, by length class.
+template <class T>
+__device__ __forceinline__ void run_chunk(const PassDesc &d, const WorkUnit &w, const BatchLaunch &b, cpx<T> *smem,
+                                          uint32_t *err)
+{
+    if (d.nu0 == d.n) {
+        run_dense<T>(d, w, b, smem);
+        return;
+    }
+    switch (d.L) {
+    case 64: run_unit<T, 6>(d, w, b, smem); break;
+    case 128: run_unit<T, 7>(d, w, b, smem); break;
+    case 256: run_unit<T, 8>(d, w, b, smem); break;
+    case 512: run_unit<T, 9>(d, w, b, smem); break;
+    case 1024: run_unit<T, 10>(d, w, b, smem); break;
+    case 2048: run_unit<T, 11>(d, w, b, smem); break;
+    case 4096: run_unit<T, 12>(d, w, b, smem); break;
+    case 8192: run_unit<T, 13>(d, w, b, smem); break;
+    case 16384: run_unit<T, 14>(d, w, b, smem); break;
+    default:
+        if (threadIdx.x == 0) atomicOr(err, kBatchErrBadLength);
+        break;
     }
 }
 
@@ -95,6 +140,24 @@ __global__ void __launch_bounds__(kBatchThreads) batch_kernel(BatchLaunch b)
         __syncthreads();  // every thread has read s_unit before it is overwritten
         if (u >= b.nunits) break;
         const WorkUnit w = b.units[u];
+        if (w.npass > 0) {
+            // a whole small item: its passes in order, every line, inside this
+            // block; the barrier after each chunk also publishes its stores to
+            // the block's later passes
+            for (int p = w.pass; p < w.pass + w.npass; ++p) {
+                const PassDesc d = b.passes[p];
+                for (int l0 = 0; l0 < d.lines; l0 += d.cap) {
+                    WorkUnit c;
+                    c.pass = p;
+                    c.line0 = l0;
+                    c.nlines = d.lines - l0 < d.cap ? d.lines - l0 : d.cap;
+                    c.split = d.split;
+                    run_chunk<T>(d, c, b, smem, err);
+                    __syncthreads();
+                }
+            }
+            continue;
+        }
         const PassDesc d = b.passes[w.pass];
         if (w.wait_pass >= 0) {
             if (threadIdx.x == 0) wait_done(done + w.wait_pass, (uint32_t)w.wait_count, err);
@@ -102,25 +165,16 @@ __global__ void __launch_bounds__(kBatchThreads) batch_kernel(BatchLaunch b)
             // the previous pass's results were written by other blocks (other XCDs)
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
-        switch (d.L) {
-        case 64: run_unit<T, 6>(d, w, b, smem); break;
-        case 128: run_unit<T, 7>(d, w, b, smem); break;
-        case 256: run_unit<T, 8>(d, w, b, smem); break;
-        case 512: run_unit<T, 9>(d, w, b, smem); break;
-        case 1024: run_unit<T, 10>(d, w, b, smem); break;
-        case 2048: run_unit<T, 11>(d, w, b, smem); break;
-        case 4096: run_unit<T, 12>(d, w, b, smem); break;
-        case 8192: run_unit<T, 13>(d, w, b, smem); break;
-        case 16384: run_unit<T, 14>(d, w, b, smem); break;
-        default:
-            if (threadIdx.x == 0) atomicOr(err, kBatchErrBadLength);
-            break;
+        run_chunk<T>(d, w, b, smem, err);
+        if (d.publish) {
+            // publish this unit's stores device-wide, then count it done
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __syncthreads();
+            if (threadIdx.x == 0)
+                __hip_atomic_fetch_add(done + w.pass, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            __syncthreads();  // the LDS is free for the next unit
         }
-        // publish this unit's stores device-wide, then count it done
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __syncthreads();
-        if (threadIdx.x == 0)
-            __hip_atomic_fetch_add(done + w.pass, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 

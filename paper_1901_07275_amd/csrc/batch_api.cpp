@@ -155,8 +155,8 @@ jt_status jt_batch_tables(jt_batch_t batch, int32_t *units, int32_t *passes)
     if (units)
         for (size_t i = 0; i < q.units.size(); ++i) {
             const jt::WorkUnit &w = q.units[i];
-            const int32_t row[6] = {w.pass, w.line0, w.nlines, w.split, w.wait_pass, w.wait_count};
-            std::memcpy(units + 6 * i, row, sizeof(row));
+            const int32_t row[7] = {w.pass, w.line0, w.nlines, w.split, w.wait_pass, w.wait_count, w.npass};
+            std::memcpy(units + 7 * i, row, sizeof(row));
         }
     if (passes) {
         std::vector<int32_t> nunits(q.passes.size(), 0);

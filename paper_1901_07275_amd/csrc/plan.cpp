@@ -672,7 +672,9 @@ void build_axis(AxisPlan &ax, int n, double a, double b, double tol, const PlanO
     int L = 64;
     while (L < n) L *= 2;
     ax.L = L;
-    ax.nu0 = (n < opt.dense_below) ? n : std::min(opt.nu0, n);
+    // dense (every degree in the direct block) below the crossover, up to the
+    // longest line the matrix-core pass takes
+    ax.nu0 = (n < opt.dense_below && n <= 1024) ? n : std::min(opt.nu0, n);
     ax.seed = opt.seed ? opt.seed : mix_key(n, a, b, tol);
 
     Rec rec = recurrence(n + 1, a, b);

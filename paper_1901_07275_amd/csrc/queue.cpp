@@ -62,6 +62,13 @@ void build_queue(const std::vector<QueueItem> &items, const jt_batch_options &op
             total *= it.ax[k]->n;
         }
         if (total >= (1LL << 31)) throw unsupported(who + "2^31 elements or more");
+        // a small multi-axis item runs whole inside one block: no cross-block
+        // waits, no device-wide fences
+        long long item_elems_axes = 0;
+        for (int k = 0; k < it.d; ++k) item_elems_axes += total;
+        const bool fuse = it.d > 1 && item_elems_axes <= kFuseMaxElems;
+        const int first_pid = (int)q.passes.size();
+        double fused_cost = 0;
         int prev = -1, prev_units = 0;
         for (int k = it.d - 1, qq = 0; k >= 0; --k, ++qq) {
             const AxisPlan &ax = *it.ax[k];
@@ -83,15 +90,26 @@ void build_queue(const std::vector<QueueItem> &items, const jt_batch_options &op
             d.max_per_bin = ax.max_per_bin;
             d.forward = it.dir == JT_FORWARD;
             const int pid = (int)q.passes.size();
-            q.passes.push_back(d);
-            q.pass_item.push_back((int32_t)i);
-            q.pass_axis.push_back(k);
-            const int S = choose_split(ax.L, d.lines, ax.rank, opt, fp32);
-            const int cap = (batch_threads(fp32) / group_threads(ax.L) / S) * group_lines(ax.L);
+            const bool dense = ax.nu0 == ax.n;  // every degree in the direct block: matrix-core units
+            if (dense && ax.n > kDenseMaxLine) throw unsupported(who + "dense axis longer than the matrix-core pass supports");
+            const int S = dense ? 1 : choose_split(ax.L, d.lines, ax.rank, opt, fp32);
+            const int cap = dense ? kDenseLinesPerUnit
+                                  : (batch_threads(fp32) / group_threads(ax.L) / S) * group_lines(ax.L);
             const int nu = (d.lines + cap - 1) / cap;
             // work of one unit: its share of the rank FFTs plus the direct block, per line set
             const double per_term = (double)ax.L * std::log2((double)ax.L);
-            const double c = ((ax.rank + S - 1) / S) * per_term * 5.0 + 2.0 * ax.nu0 * ax.n + 4.0 * ax.n;
+            const double c = dense ? 2.0 * ax.n * ax.n * cap / 8.0
+                                   : ((ax.rank + S - 1) / S) * per_term * 5.0 + 2.0 * ax.nu0 * ax.n + 4.0 * ax.n;
+            d.split = S;
+            d.cap = cap;
+            d.publish = (!fuse && k > 0) ? 1 : 0;
+            q.passes.push_back(d);
+            q.pass_item.push_back((int32_t)i);
+            q.pass_axis.push_back(k);
+            if (fuse) {
+                fused_cost += c * nu;
+                continue;
+            }
             for (int u = 0; u < nu; ++u) {
                 WorkUnit w;
                 w.pass = pid;
@@ -105,6 +123,16 @@ void build_queue(const std::vector<QueueItem> &items, const jt_batch_options &op
             }
             prev = pid;
             prev_units = nu;
+        }
+        if (fuse) {
+            WorkUnit w;
+            w.pass = first_pid;
+            w.line0 = 0;
+            w.nlines = 0;
+            w.split = 1;
+            w.npass = it.d;
+            pend.push_back({0, w, fused_cost});
+            q.cost += fused_cost;
         }
     }
     std::stable_sort(pend.begin(), pend.end(), [](const Pending &x, const Pending &y) {

@@ -236,7 +236,9 @@ struct jt_server_s {
             jt_status err = JT_OK;
             std::string msg;
             try {
-                jt::build_axis(ax, p->ax.n, p->ax.a, p->ax.b, opt.tol, jt::PlanOptions());
+                jt::PlanOptions po;
+                if (opt.dense_below > 0) po.dense_below = opt.dense_below;
+                jt::build_axis(ax, p->ax.n, p->ax.a, p->ax.b, opt.tol, po);
                 // only the sections of the server's precision go to the device
                 const size_t bytes = jt::layout_axis(ax, 0, fp32 ? jt::kPackF32 : jt::kPackF64);
                 blob.assign(bytes, 0);

@@ -8,9 +8,10 @@ import workloads
 
 
 def _items():
-    shapes = [(100,), (64, 80), (300,), (5, 6, 7), (1,), (2048,), (33, 17)]
+    shapes = [(100,), (64, 80), (300,), (5, 6, 7), (1,), (2048,), (33, 17), (800, 700), (70, 80, 90)]
     abs_ = [((0.1, 0.2),), ((0.0, 0.1), (0.2, -0.2)), ((0.3, 0.3),), ((0.0, 0.1), (0.2, 0.2), (-0.3, 0.4)),
-            ((0.1, 0.2),), ((0.2, 0.1),), ((0.1, 0.2), (0.3, -0.1))]
+            ((0.1, 0.2),), ((0.2, 0.1),), ((0.1, 0.2), (0.3, -0.1)), ((0.1, 0.1), (0.2, 0.2)),
+            ((0.1, 0.1), (0.2, 0.2), (0.3, 0.3))]
     return shapes, abs_
 
 
@@ -49,7 +50,13 @@ def test_unit_table_covers_every_line_once(prec, opts):
     assert info["threads"] == 512
     assert info["lds_bytes"] == 139264
     covered = {p: np.zeros(passes[p, 2], dtype=int) for p in range(len(passes))}
-    for pid, line0, nl, split, wp, wc in units:
+    for pid, line0, nl, split, wp, wc, npass in units:
+        if npass > 0:  # a whole small item: every line of its passes
+            assert wp == -1 and npass == len(shapes[passes[pid, 0]])
+            for p in range(pid, pid + npass):
+                assert passes[p, 0] == passes[pid, 0]
+                covered[p][:] += 1
+            continue
         assert nl >= 1 and split >= 1 and (split & (split - 1)) == 0
         if opts.get("max_split"):
             assert split <= opts["max_split"]
@@ -76,10 +83,13 @@ def test_waits_point_to_the_previous_pass_and_queue_order_is_safe():
     for q, (pid, *_rest) in enumerate(units):
         first_pos.setdefault(pid, q)
     last_pos = {pid: q for q, (pid, *_rest) in enumerate(units)}
-    for q, (pid, line0, nl, split, wp, wc) in enumerate(units):
+    fused_items = {passes[pid, 0] for pid, *_r, npass in units if npass > 0}
+    # small multi-axis items run whole; the large ones are split and wait
+    assert fused_items == {i for i, s in enumerate(shapes) if len(s) > 1 and len(s) * np.prod(s) <= 1 << 19}
+    for q, (pid, line0, nl, split, wp, wc, npass) in enumerate(units):
         item, axis = passes[pid, 0], passes[pid, 1]
         d = len(shapes[item])
-        if axis == d - 1:
+        if npass > 0 or axis == d - 1:
             assert wp == -1 and wc == 0
         else:
             assert passes[wp, 0] == item and passes[wp, 1] == axis + 1

@@ -70,10 +70,14 @@ def _check_items(jt, orc, P, out_np, limit_of):
     return worst
 
 
-MIXED_SHAPES = [(100,), (64, 80), (300,), (5, 6, 7), (1,), (2048,), (33, 17), (1000,), (40, 130), (257,)]
+# small multi-axis items run whole inside one block; (600, 900) and
+# (70, 80, 90) are large enough to be split, so their later passes wait on
+# device counters for the earlier ones
+MIXED_SHAPES = [(100,), (64, 80), (300,), (5, 6, 7), (1,), (2048,), (33, 17), (1000,), (40, 130), (257,),
+                (600, 900), (70, 80, 90)]
 MIXED_AB = [((0.1, 0.2),), ((0.0, 0.1), (0.2, -0.2)), ((0.3, 0.3),), ((0.0, 0.1), (0.2, 0.2), (-0.3, 0.4)),
             ((0.1, 0.2),), ((0.2, 0.1),), ((0.1, 0.2), (0.3, -0.1)), ((0.25, -0.35),), ((-0.4, 0.1), (0.25, -0.35)),
-            ((0.0, 0.0),)]
+            ((0.0, 0.0),), ((0.2, -0.1), (0.15, 0.05)), ((0.1, 0.1), (0.2, 0.2), (0.3, 0.3))]
 
 
 @pytest.mark.parametrize("prec,tol", [(1, 1e-7), (0, 1e-12)])
@@ -133,7 +137,7 @@ def test_batch_in_place(jt, orc):
 
 
 def test_batch_graph_replay_matches_eager(jt):
-    P = Prepared(jt, MIXED_SHAPES, MIXED_AB, [jt.FORWARD if i % 2 else jt.INVERSE for i in range(10)], 1e-7, 1,
+    P = Prepared(jt, MIXED_SHAPES, MIXED_AB, [jt.FORWARD if i % 2 else jt.INVERSE for i in range(12)], 1e-7, 1,
                  seed=6)
     P.batch.run(P.inp, P.out)
     torch.cuda.synchronize()
