@@ -73,6 +73,8 @@ struct BatchLaunch {
 constexpr int kBatchThreads = 512;
 constexpr int batch_threads(bool) { return kBatchThreads; }
 constexpr size_t batch_lds_bytes(bool fp32) { return fp32 ? (size_t)17408 * 8 : (size_t)17 * kBatchThreads * 16; }
+// Dynamic LDS of a block: the line buffers plus one word for the dequeued unit.
+constexpr size_t batch_lds_total(bool fp32) { return batch_lds_bytes(fp32) + 16; }
 // Lanes per thread for length L (lines of more than 512 lanes double up).
 inline int lanes_per_thread(int L) { return (L / 16 > kBatchThreads) ? (L / 16) / kBatchThreads : 1; }
 // Line-group shape for length L: threads per group and lines per group.

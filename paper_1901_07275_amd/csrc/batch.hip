@@ -127,9 +127,13 @@ __device__ __forceinline__ void run_chunk(const PassDesc &d, const WorkUnit &w, 
 template <class T>
 __global__ void __launch_bounds__(kBatchThreads) batch_kernel(BatchLaunch b)
 {
+    // The line buffers start at LDS offset 0 and the dequeued unit index sits
+    // after them: a static __shared__ variable would be placed first and
+    // shift the dynamic buffer off 8-byte alignment, which turns every fp64
+    // LDS access into a misaligned one.
     extern __shared__ unsigned char lds_raw[];
     cpx<T> *smem = reinterpret_cast<cpx<T> *>(lds_raw);
-    __shared__ int s_unit;
+    int &s_unit = *reinterpret_cast<int *>(lds_raw + batch_lds_bytes(sizeof(T) == 4));
     uint32_t *head = b.counters;
     uint32_t *err = b.counters + 1;
     uint32_t *done = b.counters + 2;
@@ -192,11 +196,11 @@ hipError_t launch_t(const BatchLaunch &b, hipStream_t s)
     static bool attr_set = false;
     if (!attr_set) {
         (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&batch_kernel<T>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)batch_lds_bytes(f32));
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)batch_lds_total(f32));
         (void)hipGetLastError();
         attr_set = true;
     }
-    hipLaunchKernelGGL(batch_kernel<T>, dim3((unsigned)b.grid), dim3(kBatchThreads), batch_lds_bytes(f32), s, b);
+    hipLaunchKernelGGL(batch_kernel<T>, dim3((unsigned)b.grid), dim3(kBatchThreads), batch_lds_total(f32), s, b);
     return hipGetLastError();
 }
 

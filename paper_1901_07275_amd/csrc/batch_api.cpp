@@ -143,7 +143,7 @@ jt_status jt_batch_info_get(jt_batch_t batch, jt_batch_info *info)
     info->passes = (int)batch->q.passes.size();
     info->grid = batch->grid;
     info->threads = jt::batch_threads(batch->fp32);
-    info->lds_bytes = jt::batch_lds_bytes(batch->fp32);
+    info->lds_bytes = jt::batch_lds_total(batch->fp32);
     info->cost = batch->q.cost;
     return ok();
 }
