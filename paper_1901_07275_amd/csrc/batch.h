@@ -85,8 +85,12 @@ inline int group_threads(int L)
 }
 inline int group_lines(int L) { return group_threads(L) / ((L / 16) / lanes_per_thread(L)); }
 // Multi-axis items with at most this many elements per axis pass, summed over
-// the passes, run whole inside one block.
+// the passes, run whole inside one block (when their work is also below one
+// block's share of the batch).
 constexpr long long kFuseMaxElems = 1LL << 19;
+// Persistent grid assumed when the options leave it open (one block per
+// compute unit of an MI355X).
+constexpr int kDefaultGrid = 256;
 // Dense (matrix-core) units: lines per unit and the longest dense line.
 constexpr int kDenseLinesPerUnit = 16;
 constexpr int kDenseMaxLine = 1024;

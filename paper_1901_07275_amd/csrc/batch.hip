@@ -35,30 +35,44 @@ __device__ void wait_done(const uint32_t *ctr, uint32_t need, uint32_t *err)
     }
 }
 
+// The unit functions receive the descriptors by reference, so the compiler
+// cannot see that every field is the same in all lanes; reading each one
+// through readfirstlane keeps it in scalar registers (scalar loop control and
+// address arithmetic, fewer vector registers).
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+template <class P>
+__device__ __forceinline__ P *uni(P *p)
+{
+    const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return reinterpret_cast<P *>(((unsigned long long)hi << 32) | lo);
+}
+
 // One variant per length, kept out of line: inlined together, the nine
 // variants of both directions would share one register allocation and spill.
 __device__ __forceinline__ AxisLaunch launch_of(const PassDesc &d, const BatchLaunch &b, bool fp32)
 {
     AxisLaunch a;
-    a.in = (d.in_from_out ? (const unsigned char *)b.out_base : b.in_base) + d.in_off;
-    a.out = b.out_base + d.out_off;
-    a.in_f64 = d.in_f64;
-    a.out_f64 = d.out_f64;
-    a.lines = d.lines;
-    a.stride = d.stride;
-    a.n = d.n;
-    a.L = d.L;
-    a.nu0 = d.nu0;
-    a.rank = d.rank;
-    a.max_per_bin = d.max_per_bin;
-    a.forward = d.forward;
+    a.in = uni((d.in_from_out ? (const unsigned char *)b.out_base : b.in_base) + d.in_off);
+    a.out = uni(b.out_base + d.out_off);
+    a.in_f64 = uni(d.in_f64);
+    a.out_f64 = uni(d.out_f64);
+    a.lines = uni(d.lines);
+    a.stride = uni(d.stride);
+    a.n = uni(d.n);
+    a.L = uni(d.L);
+    a.nu0 = uni(d.nu0);
+    a.rank = uni(d.rank);
+    a.max_per_bin = uni(d.max_per_bin);
+    a.forward = uni(d.forward);
     a.fp32 = fp32;
-    a.tw = d.tw;
-    a.bins = d.bins;
-    a.binptr = d.binptr;
-    a.wv = d.wv;
-    a.u = d.u;
-    a.v = d.v;
+    a.tw = uni(d.tw);
+    a.bins = uni(d.bins);
+    a.binptr = uni(d.binptr);
+    a.wv = uni(d.wv);
+    a.u = uni(d.u);
+    a.v = uni(d.v);
     return a;
 }
 
@@ -68,11 +82,11 @@ __device__ __attribute__((noinline)) void run_dense(const PassDesc &d, const Wor
                                                     cpx<T> *smem)
 {
     const AxisLaunch a = launch_of(d, b, sizeof(T) == 4);
-    const unsigned end = (unsigned)(w.line0 + w.nlines);
-    if (d.forward)
-        dense_lines<T, 1>(a, (unsigned)w.line0, end, reinterpret_cast<T *>(smem));
+    const unsigned end = (unsigned)uni(w.line0 + w.nlines);
+    if (a.forward)
+        dense_lines<T, 1>(a, (unsigned)uni(w.line0), end, reinterpret_cast<T *>(smem));
     else
-        dense_lines<T, 0>(a, (unsigned)w.line0, end, reinterpret_cast<T *>(smem));
+        dense_lines<T, 0>(a, (unsigned)uni(w.line0), end, reinterpret_cast<T *>(smem));
 }
 
 template <class T, int LOG2L>
@@ -85,14 +99,15 @@ __device__ __attribute__((noinline)) void run_unit(const PassDesc &d, const Work
         return;  // rejected on the host (the line buffer would not fit in LDS)
     } else {
         const AxisLaunch a = launch_of(d, b, sizeof(T) == 4);
-        const int S = w.split;
+        const int S = uni(w.split);
+        const int wl0 = uni(w.line0);
         const int grp = (int)threadIdx.x / G::BLOCK;
         const int vb = grp / S, sgrp = grp % S;
-        const unsigned line0 = (unsigned)w.line0 + (unsigned)(vb * G::LPB);
-        const unsigned line_end = (unsigned)(w.line0 + w.nlines);
+        const unsigned line0 = (unsigned)wl0 + (unsigned)(vb * G::LPB);
+        const unsigned line_end = (unsigned)(wl0 + uni(w.nlines));
         cpx<T> *vs = smem + vb * S * G::LPB * G::BUF;
-        const cpx<T> *tw = reinterpret_cast<const cpx<T> *>(d.tw);
-        if (d.forward)
+        const cpx<T> *tw = reinterpret_cast<const cpx<T> *>(a.tw);
+        if (a.forward)
             pass_lines<T, LOG2L, 1, VL>(a, line0, line_end, S, sgrp, (int)threadIdx.x % G::BLOCK, vs, tw);
         else
             pass_lines<T, LOG2L, 0, VL>(a, line0, line_end, S, sgrp, (int)threadIdx.x % G::BLOCK, vs, tw);

@@ -37,6 +37,27 @@ int choose_split(int L, int lines, int rank, const jt_batch_options &o, bool fp3
     return S;
 }
 
+// Shape and modelled cost of one axis pass: its split, lines per unit, unit
+// count and the work of one unit (its share of the rank FFTs plus the direct
+// block, per line set; a dense unit is one small matrix product).
+struct PassShape {
+    int S = 1, cap = 1, nu = 0;
+    double unit_cost = 0;
+};
+
+PassShape pass_shape(const AxisPlan &ax, int lines, const jt_batch_options &opt, bool fp32)
+{
+    PassShape p;
+    const bool dense = ax.nu0 == ax.n;
+    p.S = dense ? 1 : choose_split(ax.L, lines, ax.rank, opt, fp32);
+    p.cap = dense ? kDenseLinesPerUnit : (batch_threads(fp32) / group_threads(ax.L) / p.S) * group_lines(ax.L);
+    p.nu = (lines + p.cap - 1) / p.cap;
+    const double per_term = (double)ax.L * std::log2((double)ax.L);
+    p.unit_cost = dense ? 2.0 * ax.n * ax.n * p.cap / 8.0
+                        : ((ax.rank + p.S - 1) / p.S) * per_term * 5.0 + 2.0 * ax.nu0 * ax.n + 4.0 * ax.n;
+    return p;
+}
+
 }  // namespace
 
 void build_queue(const std::vector<QueueItem> &items, const jt_batch_options &opt, bool fp32, jt_dtype tin,
@@ -50,6 +71,31 @@ void build_queue(const std::vector<QueueItem> &items, const jt_batch_options &op
         double cost;
     };
     std::vector<Pending> pend;
+    // A small multi-axis item may run whole inside one block (no cross-block
+    // waits or device-wide fences), but only while its work stays below one
+    // block's share of the batch: a fused item is never split, so a larger
+    // one would become the batch's critical path (and a few large items would
+    // leave most compute units idle).
+    const int blocks = opt.grid > 0 ? opt.grid : kDefaultGrid;
+    std::vector<double> item_cost(items.size(), 0.0);
+    double total_cost = 0;
+    for (size_t i = 0; i < items.size(); ++i) {
+        const QueueItem &it = items[i];
+        if (it.d < 1 || it.d > 3) continue;  // rejected below
+        long long total = 1;
+        bool ok = true;
+        for (int k = 0; k < it.d; ++k) {
+            if (!it.ax[k]) ok = false;
+            else total *= it.ax[k]->n;
+        }
+        if (!ok || total >= (1LL << 31)) continue;
+        for (int k = 0; k < it.d; ++k) {
+            const PassShape ps = pass_shape(*it.ax[k], (int)(total / it.ax[k]->n), opt, fp32);
+            item_cost[i] += ps.unit_cost * ps.nu;
+        }
+        total_cost += item_cost[i];
+    }
+    const double fuse_cost_max = total_cost / blocks;
     for (size_t i = 0; i < items.size(); ++i) {
         const QueueItem &it = items[i];
         const std::string who = "item " + std::to_string(i) + ": ";
@@ -66,7 +112,7 @@ void build_queue(const std::vector<QueueItem> &items, const jt_batch_options &op
         // waits, no device-wide fences
         long long item_elems_axes = 0;
         for (int k = 0; k < it.d; ++k) item_elems_axes += total;
-        const bool fuse = it.d > 1 && item_elems_axes <= kFuseMaxElems;
+        const bool fuse = it.d > 1 && item_elems_axes <= kFuseMaxElems && item_cost[i] <= fuse_cost_max;
         const int first_pid = (int)q.passes.size();
         double fused_cost = 0;
         int prev = -1, prev_units = 0;
@@ -92,14 +138,9 @@ void build_queue(const std::vector<QueueItem> &items, const jt_batch_options &op
             const int pid = (int)q.passes.size();
             const bool dense = ax.nu0 == ax.n;  // every degree in the direct block: matrix-core units
             if (dense && ax.n > kDenseMaxLine) throw unsupported(who + "dense axis longer than the matrix-core pass supports");
-            const int S = dense ? 1 : choose_split(ax.L, d.lines, ax.rank, opt, fp32);
-            const int cap = dense ? kDenseLinesPerUnit
-                                  : (batch_threads(fp32) / group_threads(ax.L) / S) * group_lines(ax.L);
-            const int nu = (d.lines + cap - 1) / cap;
-            // work of one unit: its share of the rank FFTs plus the direct block, per line set
-            const double per_term = (double)ax.L * std::log2((double)ax.L);
-            const double c = dense ? 2.0 * ax.n * ax.n * cap / 8.0
-                                   : ((ax.rank + S - 1) / S) * per_term * 5.0 + 2.0 * ax.nu0 * ax.n + 4.0 * ax.n;
+            const PassShape ps = pass_shape(ax, d.lines, opt, fp32);
+            const int S = ps.S, cap = ps.cap, nu = ps.nu;
+            const double c = ps.unit_cost;
             d.split = S;
             d.cap = cap;
             d.publish = (!fuse && k > 0) ? 1 : 0;

@@ -77,7 +77,8 @@ def test_waits_point_to_the_previous_pass_and_queue_order_is_safe():
     shapes, abs_ = _items()
     plans = jt.plan_many(shapes, abs_, 1e-7)
     offs = _offsets(shapes)
-    B = jt.Batch(plans, [jt.FORWARD] * len(shapes), offs, offs)
+    # a grid of one block: every small multi-axis item is within the share
+    B = jt.Batch(plans, [jt.FORWARD] * len(shapes), offs, offs, grid=1)
     units, passes = B.tables()
     first_pos = {}
     for q, (pid, *_rest) in enumerate(units):
@@ -96,6 +97,26 @@ def test_waits_point_to_the_previous_pass_and_queue_order_is_safe():
             assert wc == passes[wp, 3]
             # every unit waited for sits earlier in the queue (no deadlock)
             assert last_pos[wp] < q
+
+
+def test_fusion_only_below_one_blocks_share():
+    """A small multi-axis item runs whole in one block only while its work is
+    below the batch's work per block: many tiny items fuse, a few mid-size
+    ones are split across blocks."""
+    def fused(shapes, **kw):
+        distinct = sorted(set(shapes))
+        one = dict(zip(distinct, jt.plan_many(distinct, [tuple((0.1, 0.1) for _ in s) for s in distinct], 1e-7)))
+        plans = [one[s] for s in shapes]
+        offs = _offsets(shapes)
+        units, passes = jt.Batch(plans, [jt.FORWARD] * len(shapes), offs, offs, **kw).tables()
+        return {passes[pid, 0] for pid, *_r, npass in units if npass > 0}
+
+    assert fused([(8, 8)] * 600) == set(range(600))
+    assert fused([(300, 300)] * 4) == set()
+    assert fused([(300, 300)] * 4, grid=1) == set(range(4))
+    # one mid-size item among many tiny ones is split, the tiny ones fuse
+    mixed = [(8, 8)] * 300 + [(300, 300)]
+    assert fused(mixed) == set(range(300))
 
 
 def test_batch_rejects_bad_arguments():
