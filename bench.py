@@ -141,9 +141,14 @@ def batched(args) -> int:
     tuning = autotune.load()
     # the tuned FFT-versus-dense crossover: 1D items are single lines, 2D items many
     db = [autotune.dense_below(1 if len(s) == 1 else min(s), jt.PREC_FP32_BULK, tuning) for s in shapes]
+    if args.dense_below >= 0:
+        db = [args.dense_below] * len(shapes)
     print("planning %d items" % len(items), file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    plans = jt.plan_many(shapes, abs_, 1e-7, dense_below=db)
+    plans = []
+    for c0 in range(0, len(shapes), 256):  # in chunks, with a progress line each
+        plans += jt.plan_many(shapes[c0:c0 + 256], abs_[c0:c0 + 256], 1e-7, dense_below=db[c0:c0 + 256])
+        print("  %d planned (%.1f s)" % (len(plans), time.perf_counter() - t0), file=sys.stderr, flush=True)
     t_plan = time.perf_counter() - t0
     print("planned in %.1f s" % t_plan, file=sys.stderr, flush=True)
     arena = jt.PlanArena(plans, dev)
@@ -335,8 +340,9 @@ def serving(args) -> int:
     arena = 16 << 30
     from paper_1901_07275_amd import autotune
 
-    S = jt.Server(arena, tol=1e-7, prec=jt.PREC_FP32_BULK, dtype=jt.F32,
-                  dense_below=autotune.dense_below(64, jt.PREC_FP32_BULK))
+    db = args.dense_below if args.dense_below >= 0 else autotune.dense_below(64, jt.PREC_FP32_BULK)
+    db1 = args.dense_below_1d if args.dense_below_1d >= 0 else autotune.dense_below(1, jt.PREC_FP32_BULK)
+    S = jt.Server(arena, tol=1e-7, prec=jt.PREC_FP32_BULK, dtype=jt.F32, dense_below=db, dense_below_1d=db1)
     print("warm-up %d requests" % len(warm), file=sys.stderr, flush=True)
     serve_stream(jt, S, warm, data, None, pool)
     # first pass over the measured requests, all offered at once: their plans
@@ -388,6 +394,7 @@ def serving(args) -> int:
         "ms_per_step": wall / len(reqs) * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "serving", "requests": len(reqs), "coeffs": coeffs, "tol": 1e-7,
+                   "dense_below": db, "dense_below_1d": db1,
                    "arena_bytes": arena, "warm_saturation_rps": sat_rps, "warm_saturation_launches": st["launches"]},
         "cold_pass": {"wall_s": wall_c, "coeffs_per_s": coeffs / wall_c,
                       "plan_hit_rate": st_c["plan_hits"] / max(1, st_c["plan_hits"] + st_c["plan_misses"]),
@@ -421,6 +428,10 @@ def main() -> int:
     ap.add_argument("--workload", default="2d", choices=["2d", "batched-1d", "batched-2d", "serving"],
                     help="2d: the 1024 x 1024 forward + inverse headline; batched-*: ragged batches")
     ap.add_argument("--count", type=int, default=4096, help="items of a batched workload (serving: requests)")
+    ap.add_argument("--dense-below", type=int, default=-1,
+                    help="batched/serving: dense-path threshold instead of the tuned one (1: FFT everywhere)")
+    ap.add_argument("--dense-below-1d", type=int, default=-1,
+                    help="serving: the same for 1D requests")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times), to calibrate "
                          "rocprofv3 FETCH_SIZE/WRITE_SIZE against known bytes")

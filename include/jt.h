@@ -277,7 +277,10 @@ typedef struct {
     int max_inflight;        /* launches in flight; 0 = 2 */
     int plan_threads;        /* host planning threads; 0 = hardware threads (at most 16) */
     jt_batch_options batch;  /* unit shaping of each launch */
-    int dense_below;         /* axes shorter than this use the dense matrix-core pass; 0 = 64 */
+    int dense_below;         /* axes shorter than this (at most 1024) use the dense matrix-core
+                                pass; 0 = 64 */
+    int dense_below_1d;      /* the same for 1D requests, whose passes have a single line (the
+                                crossover is lower there); 0 = dense_below */
 } jt_server_options;
 
 typedef struct {

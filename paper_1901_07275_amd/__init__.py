@@ -73,7 +73,8 @@ class BatchInfo(ctypes.Structure):
 class ServerOptions(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("prec", ctypes.c_int), ("in_dtype", ctypes.c_int),
                 ("out_dtype", ctypes.c_int), ("max_batch", ctypes.c_int), ("max_inflight", ctypes.c_int),
-                ("plan_threads", ctypes.c_int), ("batch", BatchOptions), ("dense_below", ctypes.c_int)]
+                ("plan_threads", ctypes.c_int), ("batch", BatchOptions), ("dense_below", ctypes.c_int),
+                ("dense_below_1d", ctypes.c_int)]
 
 
 class RequestInfo(ctypes.Structure):
@@ -493,7 +494,8 @@ class Server:
 
     def __init__(self, arena_bytes: int, tol: float = 1e-7, prec: int = PREC_FP32_BULK, dtype: int = F32,
                  max_batch: int = 0, max_inflight: int = 0, plan_threads: int = 0, device=None,
-                 max_split: int = 0, min_units: int = 0, grid: int = 0, dense_below: int = 0):
+                 max_split: int = 0, min_units: int = 0, grid: int = 0, dense_below: int = 0,
+                 dense_below_1d: int = 0):
         import torch
 
         device = torch.device(device or "cuda")
@@ -502,7 +504,7 @@ class Server:
         torch.cuda.synchronize(device)
         opt = ServerOptions(float(tol), int(prec), int(dtype), int(dtype), int(max_batch), int(max_inflight),
                             int(plan_threads), BatchOptions(int(max_split), int(min_units), int(grid)),
-                            int(dense_below))
+                            int(dense_below), int(dense_below_1d))
         h = _vp()
         _check(_lib.jt_server_create(_vp(base), int(arena_bytes), ctypes.byref(opt), ctypes.byref(h)))
         self._h = h

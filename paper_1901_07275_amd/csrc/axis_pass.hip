@@ -97,6 +97,33 @@ hipError_t launch_dense(const AxisLaunch &a, hipStream_t s)
     return hipGetLastError();
 }
 
+// Rank split S for lines held by a single wave (S waves share each line and
+// take every S-th term).  A pass costs about rounds(S) * ceil(rank / S) term
+// iterations, rounds(S) being how often its waves (blocks * S) fill the chip
+// at two waves per SIMD, the occupancy the kernels' register use allows.
+// Ties go to S = 2 in fp32; in fp64 to the larger S when the waves fill the
+// chip at most twice (balance across SIMDs) and to the smaller otherwise
+// (less partial-sum reduction).  At most 4 ways, never beyond the rank.
+// Measured on 1024^2 (ranks 19, 18) and 256^3 (rank 10): fp32 picks 2
+// everywhere, fp64 2 and 4 on 1024^2 and 1 on 256^3.
+int rank_split(long long blocks, int rank, bool fp32)
+{
+    const long long slots = 2LL * 4 * 256;
+    int best = 1;
+    long long best_cost = -1;
+    for (int S = 1; S <= 4 && S <= (rank > 1 ? rank : 1); ++S) {
+        const long long rounds = (blocks * S + slots - 1) / slots;
+        const long long cost = rounds * ((rank + S - 1) / S);
+        bool take = best_cost < 0 || cost < best_cost;
+        if (cost == best_cost) take = fp32 ? (S > 2 ? S - 2 : 2 - S) < (best > 2 ? best - 2 : 2 - best) : rounds <= 2;
+        if (take) {
+            best = S;
+            best_cost = cost;
+        }
+    }
+    return best;
+}
+
 template <class T, int LOG2L>
 hipError_t launch_t(const AxisLaunch &a, hipStream_t s)
 {
@@ -104,13 +131,7 @@ hipError_t launch_t(const AxisLaunch &a, hipStream_t s)
     const long long blocks = (a.lines + G::LPB - 1) / G::LPB;
     if (blocks <= 0) return hipSuccess;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    // rank split: aim for about 4 waves per SIMD (256 CUs x 4 SIMDs), only
-    // for lines held by a single wave, at most 4 ways and never beyond the rank
-    int S = 1;
-    if (G::BLOCK == 64) {
-        const long long target = 4LL * 4 * 256;
-        while (S < 4 && S < a.rank && blocks * S < target) S *= 2;
-    }
+    const int S = G::BLOCK == 64 ? rank_split(blocks, a.rank, sizeof(T) == 4) : 1;
     const size_t lds = ((size_t)S * G::LPB * G::BUF + (tw_mode<T, LOG2L>() == 1 ? G::L : 0)) * sizeof(cpx<T>);
     const dim3 grid((unsigned)blocks), block((unsigned)(G::BLOCK * S));
     // allow dynamic LDS beyond 64 KB (gfx950 has 160 KB per CU); once per kernel

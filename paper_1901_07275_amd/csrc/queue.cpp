@@ -37,6 +37,11 @@ int choose_split(int L, int lines, int rank, const jt_batch_options &o, bool fp3
     return S;
 }
 
+// Modelled cost of one cross-block dependency (a device-wide publish and the
+// wait for it), on the scale of the unit costs below: a few microseconds,
+// about a small FFT unit's work.
+constexpr double kSyncCost = 2e5;
+
 // Shape and modelled cost of one axis pass: its split, lines per unit, unit
 // count and the work of one unit (its share of the rank FFTs plus the direct
 // block, per line set; a dense unit is one small matrix product).
@@ -72,12 +77,16 @@ void build_queue(const std::vector<QueueItem> &items, const jt_batch_options &op
     };
     std::vector<Pending> pend;
     // A small multi-axis item may run whole inside one block (no cross-block
-    // waits or device-wide fences), but only while its work stays below one
-    // block's share of the batch: a fused item is never split, so a larger
-    // one would become the batch's critical path (and a few large items would
-    // leave most compute units idle).
+    // waits or device-wide fences).  That stretches its critical path from
+    // one unit per pass to every unit of every pass, so it is done only while
+    // the fused item stays within what bounds the batch anyway: one block's
+    // share of the total work, or the longest critical path of an item left
+    // split (a 1D item is one unit; a split item takes one unit per pass and
+    // a cross-block wait between passes).
+    // Otherwise a few mid-size items would occupy a few blocks and leave the
+    // other compute units idle.
     const int blocks = opt.grid > 0 ? opt.grid : kDefaultGrid;
-    std::vector<double> item_cost(items.size(), 0.0);
+    std::vector<double> item_cost(items.size(), 0.0), item_path(items.size(), 0.0);
     double total_cost = 0;
     for (size_t i = 0; i < items.size(); ++i) {
         const QueueItem &it = items[i];
@@ -92,10 +101,12 @@ void build_queue(const std::vector<QueueItem> &items, const jt_batch_options &op
         for (int k = 0; k < it.d; ++k) {
             const PassShape ps = pass_shape(*it.ax[k], (int)(total / it.ax[k]->n), opt, fp32);
             item_cost[i] += ps.unit_cost * ps.nu;
+            item_path[i] += ps.unit_cost + (k > 0 ? kSyncCost : 0.0);
         }
         total_cost += item_cost[i];
     }
-    const double fuse_cost_max = total_cost / blocks;
+    double fuse_cost_max = total_cost / blocks;
+    for (double p : item_path) fuse_cost_max = std::max(fuse_cost_max, p);
     for (size_t i = 0; i < items.size(); ++i) {
         const QueueItem &it = items[i];
         const std::string who = "item " + std::to_string(i) + ": ";

@@ -95,14 +95,18 @@ private:
 
 struct Key {
     int n;
+    int dense;  // 1: the whole matrix (dense matrix-core pass), 0: direct block + FFT terms
     uint64_t a, b, tol;
-    bool operator==(const Key &o) const { return n == o.n && a == o.a && b == o.b && tol == o.tol; }
+    bool operator==(const Key &o) const
+    {
+        return n == o.n && dense == o.dense && a == o.a && b == o.b && tol == o.tol;
+    }
 };
 struct KeyHash {
     size_t operator()(const Key &k) const
     {
         uint64_t h = 1469598103934665603ull;
-        for (uint64_t v : {(uint64_t)k.n, k.a, k.b, k.tol}) h = (h ^ v) * 1099511628211ull;
+        for (uint64_t v : {(uint64_t)k.n, (uint64_t)k.dense, k.a, k.b, k.tol}) h = (h ^ v) * 1099511628211ull;
         return (size_t)h;
     }
 };
@@ -186,10 +190,19 @@ struct jt_server_s {
     jt_server_s(size_t bytes) : arena(bytes) {}
 
     // ---- plan cache --------------------------------------------------
-    // Entry for (n, a, b, tol), created and queued for planning on a miss.
-    PlanEntry *find_or_plan(int n, double a, double b, bool &miss)
+    // Whether an axis of n points in a d-dimensional request keeps the whole
+    // matrix: the crossover differs between one-line passes (1D requests) and
+    // passes over many lines.
+    bool dense_axis(int n, int d) const
     {
-        Key k{n, bits(a), bits(b), bits(opt.tol)};
+        const int th = (d == 1 && opt.dense_below_1d > 0) ? opt.dense_below_1d : opt.dense_below;
+        return n < th && n <= 1024;
+    }
+
+    // Entry for (n, dense, a, b, tol), created and queued for planning on a miss.
+    PlanEntry *find_or_plan(int n, bool dense, double a, double b, bool &miss)
+    {
+        Key k{n, dense ? 1 : 0, bits(a), bits(b), bits(opt.tol)};
         auto it = cache.find(k);
         if (it != cache.end()) {
             if (it->second->state == kEvicted) {
@@ -237,7 +250,7 @@ struct jt_server_s {
             std::string msg;
             try {
                 jt::PlanOptions po;
-                if (opt.dense_below > 0) po.dense_below = opt.dense_below;
+                po.dense_below = p->key.dense ? p->ax.n + 1 : 0;
                 jt::build_axis(ax, p->ax.n, p->ax.a, p->ax.b, opt.tol, po);
                 // only the sections of the server's precision go to the device
                 const size_t bytes = jt::layout_axis(ax, 0, fp32 ? jt::kPackF32 : jt::kPackF64);
@@ -383,7 +396,7 @@ struct jt_server_s {
             if (!r->pe[0]) {
                 bool miss = false;
                 for (int k = 0; k < r->d; ++k) {
-                    r->pe[k] = find_or_plan(r->n[k], r->a[k], r->b[k], miss);
+                    r->pe[k] = find_or_plan(r->n[k], dense_axis(r->n[k], r->d), r->a[k], r->b[k], miss);
                     if (miss) st.plan_misses++;
                     else st.plan_hits++;
                     r->cold = r->cold || miss || r->pe[k]->state == kPlanning;
@@ -629,6 +642,8 @@ jt_status jt_server_create(void *dev_arena, size_t bytes, const jt_server_option
     if (o.prec != JT_PREC_FP64 && o.prec != JT_PREC_FP32_BULK) return fail(JT_EINVAL, "bad precision");
     if (o.max_batch <= 0) o.max_batch = 256;
     if (o.max_inflight <= 0) o.max_inflight = 2;
+    if (o.dense_below <= 0) o.dense_below = 64;
+    if (o.dense_below_1d <= 0) o.dense_below_1d = o.dense_below;
     if (o.plan_threads <= 0) {
         const unsigned hw = std::thread::hardware_concurrency();
         o.plan_threads = (int)std::max(1u, std::min(hw ? hw : 1u, 16u));

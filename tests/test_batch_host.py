@@ -99,10 +99,12 @@ def test_waits_point_to_the_previous_pass_and_queue_order_is_safe():
             assert last_pos[wp] < q
 
 
-def test_fusion_only_below_one_blocks_share():
-    """A small multi-axis item runs whole in one block only while its work is
-    below the batch's work per block: many tiny items fuse, a few mid-size
-    ones are split across blocks."""
+def test_fusion_keeps_the_batch_critical_path():
+    """A small multi-axis item runs whole in one block only while that does
+    not lengthen the batch: its fused work stays within the work per block or
+    the longest critical path of a split item.  Many tiny items fuse, a few
+    mid-size ones (many units per pass) are split across blocks, and items
+    whose passes are one unit each fuse however few they are."""
     def fused(shapes, **kw):
         distinct = sorted(set(shapes))
         one = dict(zip(distinct, jt.plan_many(distinct, [tuple((0.1, 0.1) for _ in s) for s in distinct], 1e-7)))
@@ -117,6 +119,8 @@ def test_fusion_only_below_one_blocks_share():
     # one mid-size item among many tiny ones is split, the tiny ones fuse
     mixed = [(8, 8)] * 300 + [(300, 300)]
     assert fused(mixed) == set(range(300))
+    # one unit per pass (lines of 40 points: 128 lines per unit): nothing to split
+    assert fused([(30, 40)] * 4) == set(range(4))
 
 
 def test_batch_rejects_bad_arguments():

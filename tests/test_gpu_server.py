@@ -169,3 +169,22 @@ def test_server_mixed_stream_sample(jt, orc):
     st = S.stats()
     print("stream stats", st, flush=True)
     S.close()
+
+
+def test_server_dense_crossover_per_regime(jt, orc):
+    """dense_below applies to multi-axis requests and dense_below_1d to 1D
+    ones: an axis of the same n is planned both ways (two cache entries)
+    and both results match the oracle."""
+    _need_gpu()
+    S = jt.Server(64 << 20, dense_below=300, dense_below_1d=100)
+    rng = np.random.default_rng(11)
+    cases = [((200,), ((0.1, 0.2),)), ((200, 40), ((0.1, 0.2), (0.3, -0.1)))]
+    for s, ab in cases:
+        x = rng.standard_normal(s).astype(np.float32)
+        out = np.full(s, np.nan, np.float32)
+        S.wait(S.submit(x, out, ab))
+        assert relerr(out, _oracle(orc, x, ab, 0)) <= 2e-5 + 20e-7 * len(s)
+    st = S.stats()
+    # n = 200 twice (FFT for the 1D request, dense for the 2D one) and n = 40
+    assert st["plans_cached"] == 3 and st["plan_misses"] == 3
+    S.close()
