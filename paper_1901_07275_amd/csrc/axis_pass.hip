@@ -64,24 +64,26 @@ __global__ void __launch_bounds__(Geo<LOG2L>::BLOCK == 64 ? 256 : Geo<LOG2L>::BL
                               (int)threadIdx.x % G::BLOCK, smem, tw);
 }
 
-// Dense pass (every degree in the direct block): 16 lines per block of four
-// waves, on the matrix cores.
+// Dense pass (every degree in the direct block): 16, 32 or 64 lines per
+// block of four waves, on the matrix cores.
 template <class T, int FWD>
 __global__ void __launch_bounds__(256) dense_pass(AxisLaunch a)
 {
     extern __shared__ unsigned char lds_raw[];
-    const unsigned line0 = blockIdx.x * (unsigned)kDenseLines;
-    const unsigned end = line0 + kDenseLines < (unsigned)a.lines ? line0 + kDenseLines : (unsigned)a.lines;
-    dense_lines<T, FWD>(a, line0, end, reinterpret_cast<T *>(lds_raw));
+    const int rows = dense_rows(a.n, (int)sizeof(T), kDenseLdsOnePass, a.lines);
+    const unsigned line0 = blockIdx.x * (unsigned)rows;
+    const unsigned end = line0 + rows < (unsigned)a.lines ? line0 + rows : (unsigned)a.lines;
+    dense_lines<T, FWD>(a, line0, end, rows, reinterpret_cast<T *>(lds_raw));
 }
 
 template <class T>
 hipError_t launch_dense(const AxisLaunch &a, hipStream_t s)
 {
-    const long long blocks = (a.lines + kDenseLines - 1) / kDenseLines;
+    const int rows = dense_rows(a.n, (int)sizeof(T), kDenseLdsOnePass, a.lines);
+    const long long blocks = (a.lines + rows - 1) / rows;
     if (blocks <= 0) return hipSuccess;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    const size_t lds = dense_lds_bytes(a.n, sizeof(T) == 4);
+    const size_t lds = dense_lds_bytes(a.n, rows, (int)sizeof(T));
     static bool attr_set[2] = {false, false};
     if (!attr_set[a.forward ? 1 : 0]) {
         const void *fn = a.forward ? reinterpret_cast<const void *>(&dense_pass<T, 1>)

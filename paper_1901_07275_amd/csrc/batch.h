@@ -16,6 +16,8 @@
 
 #include <cstdint>
 
+#include "dense_shape.h"
+
 namespace jt {
 
 // One axis pass of one item.  Tensor pointers are byte offsets from the
@@ -91,9 +93,13 @@ constexpr long long kFuseMaxElems = 1LL << 19;
 // Persistent grid assumed when the options leave it open (one block per
 // compute unit of an MI355X).
 constexpr int kDefaultGrid = 256;
-// Dense (matrix-core) units: lines per unit and the longest dense line.
-constexpr int kDenseLinesPerUnit = 16;
-constexpr int kDenseMaxLine = 1024;
+// Dense (matrix-core) units: lines per unit (as many as the block's LDS
+// holds: 64, 32 or 16) and the longest dense line.
+inline int dense_unit_lines(int n, int lines, bool fp32)
+{
+    return dense_rows(n, fp32 ? 4 : 8, batch_lds_bytes(fp32), lines);
+}
+constexpr int kDenseMaxLine = kDenseMax;
 
 // Zero the counters and launch the persistent kernel on `stream`.
 hipError_t launch_batch(const BatchLaunch &b, hipStream_t stream);

@@ -83,10 +83,11 @@ __device__ __attribute__((noinline)) void run_dense(const PassDesc &d, const Wor
 {
     const AxisLaunch a = launch_of(d, b, sizeof(T) == 4);
     const unsigned end = (unsigned)uni(w.line0 + w.nlines);
+    const int rows = uni(d.cap);  // lines per dense unit: 16, 32 or 64
     if (a.forward)
-        dense_lines<T, 1>(a, (unsigned)uni(w.line0), end, reinterpret_cast<T *>(smem));
+        dense_lines<T, 1>(a, (unsigned)uni(w.line0), end, rows, reinterpret_cast<T *>(smem));
     else
-        dense_lines<T, 0>(a, (unsigned)uni(w.line0), end, reinterpret_cast<T *>(smem));
+        dense_lines<T, 0>(a, (unsigned)uni(w.line0), end, rows, reinterpret_cast<T *>(smem));
 }
 
 template <class T, int LOG2L>

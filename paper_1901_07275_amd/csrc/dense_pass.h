@@ -3,14 +3,15 @@
 // terms), and a pass over many lines is a small matrix product
 //   forward:  out[line][j] = sum_k WV[k][j] in[line][k]   (Out = In * WV)
 //   inverse:  out[line][k] = sum_j WV[k][j] in[line][j]   (Out = In * WV^T)
-// computed with 16 x 16 x 4 MFMA tiles: 16 lines by 16 outputs per wave,
-// accumulating over the degrees four at a time (fp32 tiles for the fp32-bulk
-// path, fp64 tiles for the fp64 path).  A block first stages its 16 input
-// lines in LDS, so passes that work in place are safe.
+// computed with 16 x 16 x 4 MFMA tiles (16 lines by 16 outputs), accumulating
+// over the degrees four at a time (fp32 tiles for the fp32-bulk path, fp64
+// tiles for the fp64 path).  A block first stages its 16, 32 or 64 input
+// lines in LDS (as many as fit), so passes that work in place are safe.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
+#include "dense_shape.h"
 #include "launch.h"
 
 namespace jt {
@@ -43,36 +44,28 @@ struct Mfma<double> {
     static __device__ __forceinline__ int row(int lane, int i) { return (lane >> 4) + 4 * i; }
 };
 
-// Lines of a dense pass held by one block, and the longest dense line.
-constexpr int kDenseLines = 16;
-constexpr int kDenseMax = 1024;
-// LDS row stride (elements) of the staged lines: odd, against bank conflicts.
-__host__ __device__ constexpr int dense_ld(int n) { return n | 1; }
-// Dynamic LDS a dense block needs.
-__host__ __device__ constexpr size_t dense_lds_bytes(int n, bool fp32)
-{
-    return (size_t)kDenseLines * (size_t)dense_ld(n) * (fp32 ? 4 : 8);
-}
-
-// All threads of the block: lines line0 .. line0 + 15 (those below line_end).
-// smem holds dense_lds_bytes(n) bytes.
-template <class T, int FWD>
-__device__ __forceinline__ void dense_lines(const AxisLaunch &a, unsigned line0, unsigned line_end, T *smem)
+// All threads of the block: lines line0 .. line0 + rows - 1 (those below
+// line_end), rows = 16 * RT.  smem holds dense_lds_bytes(n, rows) bytes.  Each
+// wave takes 16-column tiles of the output and computes the RT row tiles of
+// a column tile together, so a loaded matrix column serves RT MFMAs.
+template <class T, int FWD, int RT>
+__device__ __forceinline__ void dense_tiles(const AxisLaunch &a, unsigned line0, unsigned line_end, T *smem)
 {
     using M = Mfma<T>;
+    constexpr int R = 16 * RT;
     const int n = a.n, ld = dense_ld(n);
     const unsigned stride = (unsigned)a.stride;
     // stage the lines (zero past the end); consecutive threads read along the
     // axis for contiguous lines, across lines for strided ones
-    const int total = kDenseLines * n;
+    const int total = R * n;
     for (int e = (int)threadIdx.x; e < total; e += (int)blockDim.x) {
         int r, k;
         if (stride == 1u) {
             r = e / n;
             k = e - r * n;
         } else {
-            k = e / kDenseLines;
-            r = e - k * kDenseLines;
+            k = e / R;
+            r = e - k * R;
         }
         const unsigned line = line0 + (unsigned)r;
         T v = 0;
@@ -92,29 +85,46 @@ __device__ __forceinline__ void dense_lines(const AxisLaunch &a, unsigned line0,
     for (int c0 = 16 * (int)(threadIdx.x >> 6); c0 < n; c0 += 16 * waves) {
         const int bcol = c0 + (lane & 15);
         const bool bcol_ok = bcol < n;
-        typename M::acc c = {0, 0, 0, 0};
+        const typename M::acc zero = {0, 0, 0, 0};
+        typename M::acc c[RT];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) c[rt] = zero;
         for (int k0 = 0; k0 < n; k0 += 4) {
             const int k = k0 + kl;
-            T av = 0, bv = 0;
-            if (k < n) {
-                av = smem[arow * ld + k];
-                if (bcol_ok) bv = FWD ? wv[k * n + bcol] : wv[bcol * n + k];
+            const bool k_ok = k < n;
+            T bv = 0;
+            if (k_ok && bcol_ok) bv = FWD ? wv[k * n + bcol] : wv[bcol * n + k];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) {
+                const T av = k_ok ? smem[(rt * 16 + arow) * ld + k] : (T)0;
+                c[rt] = M::step(av, bv, c[rt]);
             }
-            c = M::step(av, bv, c);
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const unsigned line = line0 + (unsigned)M::row(lane, i);
-            if (line < line_end && bcol_ok) {
-                const unsigned outer = line / stride;
-                const unsigned o = outer * (unsigned)n * stride + (line - outer * stride) + (unsigned)bcol * stride;
-                if (a.out_f64)
-                    reinterpret_cast<double *>(a.out)[o] = (double)c[i];
-                else
-                    reinterpret_cast<float *>(a.out)[o] = (float)c[i];
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const unsigned line = line0 + (unsigned)(rt * 16 + M::row(lane, i));
+                if (line < line_end && bcol_ok) {
+                    const unsigned outer = line / stride;
+                    const unsigned o = outer * (unsigned)n * stride + (line - outer * stride) + (unsigned)bcol * stride;
+                    if (a.out_f64)
+                        reinterpret_cast<double *>(a.out)[o] = (double)c[rt][i];
+                    else
+                        reinterpret_cast<float *>(a.out)[o] = (float)c[rt][i];
+                }
             }
-        }
     }
+}
+
+// Dispatch on the block's line count (16, 32 or 64).
+template <class T, int FWD>
+__device__ __forceinline__ void dense_lines(const AxisLaunch &a, unsigned line0, unsigned line_end, int rows,
+                                            T *smem)
+{
+    if (rows == 64) dense_tiles<T, FWD, 4>(a, line0, line_end, smem);
+    else if (rows == 32) dense_tiles<T, FWD, 2>(a, line0, line_end, smem);
+    else dense_tiles<T, FWD, 1>(a, line0, line_end, smem);
 }
 
 }  // namespace dev

@@ -55,7 +55,8 @@ PassShape pass_shape(const AxisPlan &ax, int lines, const jt_batch_options &opt,
     PassShape p;
     const bool dense = ax.nu0 == ax.n;
     p.S = dense ? 1 : choose_split(ax.L, lines, ax.rank, opt, fp32);
-    p.cap = dense ? kDenseLinesPerUnit : (batch_threads(fp32) / group_threads(ax.L) / p.S) * group_lines(ax.L);
+    p.cap = dense ? dense_unit_lines(ax.n, lines, fp32)
+                  : (batch_threads(fp32) / group_threads(ax.L) / p.S) * group_lines(ax.L);
     p.nu = (lines + p.cap - 1) / p.cap;
     const double per_term = (double)ax.L * std::log2((double)ax.L);
     p.unit_cost = dense ? 2.0 * ax.n * ax.n * p.cap / 8.0
