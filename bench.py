@@ -75,12 +75,16 @@ def percentile(xs, q):
 
 
 def time_path(jt, torch, plan, alpha, prec, steps, warmup):
+    """One step = the forward transform (axes d-1 .. 0) then the inverse of
+    its result; every axis-pass launch is bracketed by HIP events on the
+    launch stream."""
     dev = alpha.device
     g = torch.empty_like(alpha)
     back = torch.empty_like(alpha)
     stream = torch.cuda.current_stream(dev)
-    launches = [(1, jt.FORWARD, alpha, g), (0, jt.FORWARD, g, g),
-                (1, jt.INVERSE, g, back), (0, jt.INVERSE, back, back)]
+    axes = list(range(plan.d - 1, -1, -1))
+    launches = [(ax, jt.FORWARD, alpha if i == 0 else g, g) for i, ax in enumerate(axes)]
+    launches += [(ax, jt.INVERSE, g if i == 0 else back, back) for i, ax in enumerate(axes)]
 
     def step(record):
         evs = []
@@ -109,6 +113,169 @@ def time_path(jt, torch, plan, alpha, prec, steps, warmup):
         for i in range(len(launches)):
             launch_ms[i].append(evs[i].elapsed_time(evs[i + 1]))
     return wall, step_ms, launch_ms, g, back
+
+
+def cpu_cores() -> int:
+    try:
+        from threadpoolctl import threadpool_info
+
+        return int(max([p.get("num_threads", 1) for p in threadpool_info()] or [os.cpu_count() or 1]))
+    except Exception:
+        return os.cpu_count() or 1
+
+
+def oracle_rate(fn, seconds: float) -> tuple:
+    """Repeat fn() for about `seconds`; returns (repetitions, seconds used)."""
+    reps, t_used = 0, 0.0
+    t0 = time.perf_counter()
+    while t_used < seconds or reps == 0:
+        fn()
+        reps += 1
+        t_used = time.perf_counter() - t0
+    return reps, t_used
+
+
+def workload_3d(args) -> int:
+    """The 3D 256^3 transform, (a, b) = (0.3, 0.3) on every axis, tol 1e-7,
+    fp32 bulk (fp64 beside it): one step is a forward and an inverse
+    transform, six axis-pass launches."""
+    import torch
+
+    import oracle
+    import paper_1901_07275_amd as jt
+
+    cfg = workloads.C3
+    dev = torch.device("cuda:0")
+    t_plan = time.perf_counter()
+    plan = jt.Plan(cfg["n"], cfg["ab"], cfg["tol"]).bind(dev)
+    t_plan = time.perf_counter() - t_plan
+    infos = [plan.info(i) for i in range(plan.d)]
+    al_np = workloads.config_input(cfg)
+    alpha = torch.from_numpy(al_np).to(dev)
+    coeffs = int(np.prod(cfg["n"]))
+    g_ref = oracle.forward(al_np, cfg["ab"])
+    res = {}
+    for name, prec in (("fp32", jt.PREC_FP32_BULK), ("fp64", jt.PREC_FP64)):
+        wall, step_ms, launch_ms, g, back = time_path(jt, torch, plan, alpha, prec, args.steps, args.warmup)
+        ms = float(np.mean(step_ms))
+        axes = list(range(plan.d - 1, -1, -1)) * 2
+        flops = [axis_flops(infos[a]["n"], infos[a]["L"], infos[a]["nu0"], infos[a]["rank"], coeffs // infos[a]["n"])
+                 for a in axes]
+        lm = [float(np.mean(x)) for x in launch_ms]
+        peak = PEAK_FP32 if name == "fp32" else PEAK_FP64
+        ach = float(np.mean(flops)) / (float(np.mean(lm)) * 1e-3) / 1e12
+        gg, bb = g.cpu().numpy(), back.cpu().numpy()
+        res[name] = {"ms_per_step": ms, "p50_ms": percentile(step_ms, 50), "p99_ms": percentile(step_ms, 99),
+                     "value": 2.0 * coeffs / (ms * 1e-3), "launch_ms": lm,
+                     "rel_l2_forward": float(np.linalg.norm(gg - g_ref) / np.linalg.norm(g_ref)),
+                     "rel_l2_roundtrip": float(np.linalg.norm(bb - al_np) / np.linalg.norm(al_np)),
+                     "roofline": {"bound": "alu", "achieved": ach, "peak": peak / 1e12, "unit": "TFLOP/s",
+                                  "frac": ach / (peak / 1e12), "traffic": None,
+                                  "kernel": "axis_pass<%s,8>" % ("float" if name == "fp32" else "double"),
+                                  "flops_per_launch": float(np.mean(flops))}}
+    cpu = None
+    if not args.no_cpu_baseline:
+        reps, t_used = oracle_rate(lambda: oracle.inverse(oracle.forward(al_np, cfg["ab"]), cfg["ab"]),
+                                   args.cpu_seconds)
+        cpu = {"value": 2.0 * coeffs * reps / t_used, "unit": "coeffs/s", "cores": cpu_cores(), "kind": "oracle",
+               "sample": "%d forward+inverse passes of the full 256^3 workload (dense oracle matrices along "
+                         "each axis, fp64), %.1f s" % (reps, t_used)}
+    head = res["fp32"]
+    line = {"metric": "coeffs/s, 3D n=256 Jacobi transform, FP32 bulk (FP64 beside it) at stated rel-l2",
+            "value": head["value"], "unit": "coeffs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "3d_n256_forward_plus_inverse", "n": list(cfg["n"]),
+                       "ab": [list(p) for p in cfg["ab"]], "tol": cfg["tol"], "ranks": [i["rank"] for i in infos],
+                       "plan_seconds": t_plan, "step": "one forward + one inverse transform (6 axis-pass launches)"},
+            "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"], "rel_l2_forward": head["rel_l2_forward"],
+            "rel_l2_roundtrip": head["rel_l2_roundtrip"], "roofline": head["roofline"], "cpu_baseline": cpu,
+            "fp32": head, "fp64": res["fp64"]}
+    print(json.dumps(line))
+    return 0
+
+
+def workload_1d(args) -> int:
+    """One 1D transform of n = 1024 ((a, b) = (0.25, -0.35), tol 1e-12):
+    per-launch latency over `steps` forward launches, eager and replayed
+    from a captured HIP graph, fp64 and fp32 bulk."""
+    import torch
+
+    import oracle
+    import paper_1901_07275_amd as jt
+
+    cfg = workloads.C1
+    dev = torch.device("cuda:0")
+    plan = jt.Plan(cfg["n"], cfg["ab"], cfg["tol"]).bind(dev)
+    info = plan.info(0)
+    al_np = workloads.config_input(cfg)
+    alpha = torch.from_numpy(al_np).to(dev)
+    n = cfg["n"][0]
+    g_ref = oracle.forward(al_np, cfg["ab"])
+    stream = torch.cuda.current_stream(dev)
+    res = {}
+    for name, prec in (("fp64", jt.PREC_FP64), ("fp32", jt.PREC_FP32_BULK)):
+        out = torch.empty_like(alpha)
+        for _ in range(args.warmup):
+            plan.forward(alpha, out, prec=prec)
+        torch.cuda.synchronize()
+        evs = []
+        for _ in range(args.steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            plan.forward(alpha, out, prec=prec)
+            e1.record(stream)
+            evs.append((e0, e1))
+        torch.cuda.synchronize()
+        eager = [a.elapsed_time(b) for a, b in evs]
+        eager_out = out.cpu().numpy()
+        # the same launch captured once and replayed
+        gout = torch.empty_like(alpha)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            plan.forward(alpha, gout, prec=prec)
+        torch.cuda.synchronize()
+        evs = []
+        for _ in range(args.steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            graph.replay()
+            e1.record(stream)
+            evs.append((e0, e1))
+        torch.cuda.synchronize()
+        replay = [a.elapsed_time(b) for a, b in evs]
+        assert np.array_equal(gout.cpu().numpy(), eager_out), "graph replay differs from the eager launch"
+        ms = float(np.mean(eager))
+        nbytes = (16.0 if name == "fp64" else 8.0) * info["rank"] * (n + info["L"]) \
+            + (8.0 if name == "fp64" else 4.0) * info["nu0"] * n + 4.0 * n + 16.0 * n
+        res[name] = {"value": n / (ms * 1e-3), "mean_ms": ms, "p50_ms": percentile(eager, 50),
+                     "p99_ms": percentile(eager, 99), "graph_mean_ms": float(np.mean(replay)),
+                     "graph_p50_ms": percentile(replay, 50), "graph_p99_ms": percentile(replay, 99),
+                     "rel_l2_forward": float(np.linalg.norm(eager_out - g_ref) / np.linalg.norm(g_ref)),
+                     "bytes_per_launch": nbytes, "hbm_gbs": nbytes / (ms * 1e-3) / 1e9}
+        del graph
+    head = res["fp64"]
+    cpu = None
+    if not args.no_cpu_baseline:
+        reps, t_used = oracle_rate(lambda: oracle.forward(al_np, cfg["ab"]), min(args.cpu_seconds, 5.0))
+        cpu = {"value": n * reps / t_used, "unit": "coeffs/s", "cores": cpu_cores(), "kind": "oracle",
+               "sample": "%d forward transforms of the 1D n=1024 workload (dense oracle matrix built and "
+                         "applied each time, fp64), %.1f s" % (reps, t_used)}
+    line = {"metric": "coeffs/s and p50/p99 launch latency, one 1D n=1024 transform (plain FP64; FP32 bulk beside)",
+            "value": head["value"], "unit": "coeffs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": head["mean_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "1d_n1024_forward", "n": list(cfg["n"]), "ab": [list(p) for p in cfg["ab"]],
+                       "tol": cfg["tol"], "rank": info["rank"], "L": info["L"],
+                       "step": "one forward transform (1 axis-pass launch)"},
+            "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"], "rel_l2_forward": head["rel_l2_forward"],
+            "roofline": {"bound": "hbm", "achieved": head["hbm_gbs"], "peak": 8000.0, "unit": "GB/s",
+                         "frac": head["hbm_gbs"] / 8000.0, "traffic": None, "kernel": "axis_pass<double,10>",
+                         "bytes_per_launch": head["bytes_per_launch"],
+                         "note": "a single line: launch latency, not bandwidth, bounds it"},
+            "cpu_baseline": cpu, "fp64": head, "fp32": res["fp32"]}
+    print(json.dumps(line))
+    return 0
 
 
 def factor_bytes_fp32(info: dict, lines: int) -> float:
@@ -425,8 +592,9 @@ def main() -> int:
     ap.add_argument("--rates", type=lambda v: [float(x) for x in v.split(",")], default=[0.5, 0.8, 0.95],
                     help="serving: offered loads as fractions of the measured saturation rate")
     ap.add_argument("--fp64-count", type=int, default=200, help="serving: requests timed on the fp64 path")
-    ap.add_argument("--workload", default="2d", choices=["2d", "batched-1d", "batched-2d", "serving"],
-                    help="2d: the 1024 x 1024 forward + inverse headline; batched-*: ragged batches")
+    ap.add_argument("--workload", default="2d", choices=["2d", "1d", "3d", "batched-1d", "batched-2d", "serving"],
+                    help="2d: the 1024 x 1024 forward + inverse headline; 1d: launch latency of one n = 1024 "
+                         "transform; 3d: the 256^3 transform; batched-*: ragged batches; serving: request stream")
     ap.add_argument("--count", type=int, default=4096, help="items of a batched workload (serving: requests)")
     ap.add_argument("--dense-below", type=int, default=-1,
                     help="batched/serving: dense-path threshold instead of the tuned one (1: FFT everywhere)")
@@ -455,6 +623,10 @@ def main() -> int:
 
     if args.workload == "serving":
         return serving(args)
+    if args.workload == "3d":
+        return workload_3d(args)
+    if args.workload == "1d":
+        return workload_1d(args)
     if args.workload != "2d":
         return batched(args)
 

@@ -197,6 +197,19 @@ __device__ __forceinline__ void line_sum(double *v, double *red, int t)
     }
 }
 
+// Four consecutive values from a 16-byte aligned address (global or LDS).
+template <class T>
+__device__ __forceinline__ void load4(const T *p, T (&o)[4])
+{
+    if constexpr (sizeof(T) == 4) {
+        const float4 v = *reinterpret_cast<const float4 *>(p);
+        o[0] = v.x, o[1] = v.y, o[2] = v.z, o[3] = v.w;
+    } else {
+        const double2 a = reinterpret_cast<const double2 *>(p)[0], b = reinterpret_cast<const double2 *>(p)[1];
+        o[0] = a.x, o[1] = a.y, o[2] = b.x, o[3] = b.y;
+    }
+}
+
 // Shape of one line of length L = 2^LOG2L: P = L/16 lanes, each holding 16
 // elements.  A thread carries VL lanes (p and p + TPL, ...), so a line takes
 // TPL = P / VL threads; lines shorter than a wave share one (LPB lines per
@@ -580,13 +593,46 @@ __device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, 
         double *red = reinterpret_cast<double *>(buf);  // free until the first term
         const int nchunks = (nu0 + KC - 1) / KC;
         const int rounds = (nchunks + S - 1) / S;
+        // When n is a multiple of 4 the line is staged in LDS (behind the
+        // sums in red) and each thread takes groups of four consecutive
+        // nodes, so a degree's row of WV is read with 16-byte loads: the
+        // block re-reads WV for every line, and four times fewer (wider)
+        // loads is what this block's time depends on.
+        const bool vec4 = (n & 3) == 0;  // uniform
+        T *gs = reinterpret_cast<T *>(reinterpret_cast<unsigned char *>(buf) + (G::TPL > 64 ? 1024 : 256));
+        if (vec4) {
+#pragma unroll
+            for (int h = 0; h < VL; ++h)
+#pragma unroll
+                for (int q = 0; q < 16; ++q) gs[pv[h] + G::P * q] = x[h][q];  // zero beyond n
+            sync_line<G::TPL>();
+        }
+        constexpr int NI = G::L / (4 * G::TPL);  // four-node groups per thread
         for (int rd = 0; rd < rounds; ++rd) {
             const int ch = rd * S + sgrp;
             const int k0 = ch * KC;
             double part[KC];
 #pragma unroll
             for (int c = 0; c < KC; ++c) part[c] = 0.0;
-            if (ch < nchunks) {
+            if (ch < nchunks && vec4) {
+                const int t = tid % G::TPL;
+#pragma unroll
+                for (int i = 0; i < NI; ++i) {
+                    const int j = 4 * (t + G::TPL * i);
+                    if (j < n) {
+                        T g4[4];
+                        load4(gs + j, g4);
+#pragma unroll
+                        for (int c = 0; c < KC; ++c)
+                            if (k0 + c < nu0) {
+                                T w4[4];
+                                load4(wv + (k0 + c) * n + j, w4);
+#pragma unroll
+                                for (int e = 0; e < 4; ++e) part[c] += (double)w4[e] * (double)g4[e];
+                            }
+                    }
+                }
+            } else if (ch < nchunks) {
 #pragma unroll
                 for (int h = 0; h < VL; ++h)
 #pragma unroll
