@@ -44,14 +44,41 @@ def axis_flops(n: int, L: int, nu0: int, rank: int, lines: int) -> float:
     return per_line * lines
 
 
-def kernel_source_hash() -> str:
-    """sha256[:16] over the sources the axis-pass kernel is built from."""
+def source_hash(names) -> str:
+    """sha256[:16] over the named files of the package (csrc/ unless a path is given)."""
     import hashlib
 
     h = hashlib.sha256()
-    for name in ("axis_pass.hip", "fft_line.h", "launch.h"):
-        h.update(open(os.path.join(ROOT, "paper_1901_07275_amd", "csrc", name), "rb").read())
+    for name in names:
+        path = os.path.join(ROOT, "paper_1901_07275_amd", name if "/" in name else os.path.join("csrc", name))
+        h.update(open(path, "rb").read())
     return h.hexdigest()[:16]
+
+
+def kernel_source_hash() -> str:
+    """sha256[:16] over the sources the axis-pass kernel is built from."""
+    return source_hash(("axis_pass.hip", "fft_line.h", "launch.h", "dense_pass.h", "dense_shape.h"))
+
+
+def batch_source_hash() -> str:
+    """sha256[:16] over what decides the batch kernel's work: its sources,
+    the queue builder and the tuned crossover table."""
+    return source_hash(("batch.hip", "batch.h", "queue.cpp", "fft_line.h", "dense_pass.h", "dense_shape.h",
+                        "launch.h", "./tuning.json"))
+
+
+def measured_batch_traffic(workload: str, items: int):
+    """HBM bytes per launch of the batch kernel on this batched workload from
+    the committed rocprofv3 summary, or None (other workload, or sources
+    changed since the counters were taken)."""
+    prof = os.path.join(ROOT, "profiles", "batch_kernel_%s_traffic.json" % workload.replace("batched-", ""))
+    try:
+        rec = json.load(open(prof))
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256_16") != batch_source_hash() or rec.get("items") != items:
+        return None
+    return float(rec["hbm_bytes"])
 
 
 def measured_traffic(kernel_prefix: str):
@@ -391,8 +418,8 @@ def batched(args) -> int:
                    "plan_seconds": t_plan, "graph": True, "tuning": tuning.get("source"),
                    "dense_items": int(sum(1 for p in plans if p.info(0)["nu0"] == p.info(0)["n"]))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
-                     "frac": achieved / 8000.0, "traffic": None, "kernel": "batch_kernel<float>",
-                     "bytes_per_launch": nbytes},
+                     "frac": achieved / 8000.0, "traffic": measured_batch_traffic(args.workload, len(items)),
+                     "kernel": "batch_kernel<float>", "bytes_per_launch": nbytes},
         "sample_rel_l2_max": max(errs) if errs else None,
         "fp64_one_at_a_time": {"ms": t64, "value": coeffs_sel / (t64 * 1e-3), "items": len(sel),
                                "launches": int(sum(len(shapes[i]) for i in sel))},

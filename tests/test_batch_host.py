@@ -177,3 +177,33 @@ def test_batched_workload_recipe_is_seeded():
     assert all(64 <= x[0] <= 16384 for x in a)
     c = workloads.batch_2d(8)
     assert all(32 <= m <= 512 for x in c for m in x[0])
+
+
+def test_dense_units_hold_as_many_lines_as_lds_allows():
+    """A dense (matrix-core) unit stages 64, 32 or 16 lines: the most whose
+    rows fit the block's 139264 bytes of LDS, and no more than the pass has."""
+    def rows(n, elem, lines):
+        r = 64
+        while r > 16 and (r * (n | 1) * elem > 139264 or r // 2 >= lines):
+            r //= 2
+        return r
+
+    shapes = [(1000, 300), (7, 500)]
+    abs_ = [((0.1, 0.2), (0.3, -0.1)), ((0.2, 0.2), (0.1, 0.0))]
+    for prec, elem in ((jt.PREC_FP32_BULK, 4), (jt.PREC_FP64, 8)):
+        plans = jt.plan_many(shapes, abs_, 1e-7, dense_below=[1025, 1025])
+        offs = _offsets(shapes)
+        units, passes = jt.Batch(plans, [jt.FORWARD] * 2, offs, offs, jt.F64, jt.F64, prec, grid=256).tables()
+        seen = 0
+        for pid in range(len(passes)):
+            item, axis = passes[pid, 0], passes[pid, 1]
+            s = shapes[item]
+            n, lines = s[axis], int(np.prod(s)) // s[axis]
+            mine = units[units[:, 0] == pid]
+            if len(mine) == 0 or mine[0, 6] > 0:
+                continue  # fused into one unit
+            want = rows(n, elem, lines)
+            assert np.all(mine[:-1, 2] == want) and 1 <= mine[-1, 2] <= want, (prec, s, axis)
+            assert mine[:, 2].sum() == lines
+            seen += 1
+        assert seen >= 2
