@@ -392,7 +392,7 @@ def batched(args) -> int:
     # the plain fp64 path on the same GPU: the same items one transform at a
     # time (items it supports: n <= 8192 per axis), and the batch restricted
     # to those items for a like-for-like ratio
-    sel = [i for i, s in enumerate(shapes) if max(s) <= 8192]
+    sel = [i for i, s in enumerate(shapes) if max(s) <= 8192] if not args.no_fp64_compare else []
     dev_x = [torch.from_numpy(xs[i]).to(dev) for i in sel]
     dev_g = [torch.empty_like(x) for x in dev_x]
     for i, x, g in zip(sel, dev_x, dev_g):
@@ -404,7 +404,7 @@ def batched(args) -> int:
         plans[i].forward(x, g, prec=jt.PREC_FP64)
     e1.record(stream)
     torch.cuda.synchronize()
-    t64 = e0.elapsed_time(e1)
+    t64 = e0.elapsed_time(e1) if sel else float("nan")
     coeffs_sel = int(sum(sizes[i] for i in sel))
     info = B.info()
     line = {
@@ -421,8 +421,8 @@ def batched(args) -> int:
                      "frac": achieved / 8000.0, "traffic": measured_batch_traffic(args.workload, len(items)),
                      "kernel": "batch_kernel<float>", "bytes_per_launch": nbytes},
         "sample_rel_l2_max": max(errs) if errs else None,
-        "fp64_one_at_a_time": {"ms": t64, "value": coeffs_sel / (t64 * 1e-3), "items": len(sel),
-                               "launches": int(sum(len(shapes[i]) for i in sel))},
+        "fp64_one_at_a_time": ({"ms": t64, "value": coeffs_sel / (t64 * 1e-3), "items": len(sel),
+                                "launches": int(sum(len(shapes[i]) for i in sel))} if sel else None),
     }
     print(json.dumps(line))
     del arena
@@ -627,6 +627,8 @@ def main() -> int:
                     help="batched/serving: dense-path threshold instead of the tuned one (1: FFT everywhere)")
     ap.add_argument("--dense-below-1d", type=int, default=-1,
                     help="serving: the same for 1D requests")
+    ap.add_argument("--no-fp64-compare", action="store_true",
+                    help="batched: skip the one-at-a-time fp64 comparison (for profiler runs)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times), to calibrate "
                          "rocprofv3 FETCH_SIZE/WRITE_SIZE against known bytes")
