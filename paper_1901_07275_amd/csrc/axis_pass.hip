@@ -45,9 +45,12 @@ __device__ __forceinline__ unsigned block_line(unsigned lpb)
 }
 
 // The one-pass kernel: a block holds S split groups that share the same
-// lines (rank split, only for lines held by a single wave).
-template <class T, int LOG2L, int FWD>
-__global__ void __launch_bounds__(Geo<LOG2L>::BLOCK == 64 ? 256 : Geo<LOG2L>::BLOCK) axis_pass(AxisLaunch a)
+// lines (rank split, only for lines held by a single wave).  WIDE: blocks of
+// up to eight single-wave groups, for passes with too few lines to fill the
+// chip (a 1D transform is one line), where more groups per line shorten it.
+template <class T, int LOG2L, int FWD, int WIDE>
+__global__ void __launch_bounds__(WIDE ? 512 : (Geo<LOG2L>::BLOCK == 64 ? 256 : Geo<LOG2L>::BLOCK))
+    axis_pass(AxisLaunch a)
 {
     using G = Geo<LOG2L>;
     extern __shared__ unsigned char lds_raw[];
@@ -107,13 +110,16 @@ hipError_t launch_dense(const AxisLaunch &a, hipStream_t s)
 // chip at most twice (balance across SIMDs) and to the smaller otherwise
 // (less partial-sum reduction).  At most 4 ways, never beyond the rank.
 // Measured on 1024^2 (ranks 19, 18) and 256^3 (rank 10): fp32 picks 2
-// everywhere, fp64 2 and 4 on 1024^2 and 1 on 256^3.
+// everywhere, fp64 2 and 4 on 1024^2 and 1 on 256^3.  Passes of at most 256
+// blocks (fewer than the compute units) may go to 8 ways in the wide kernel.
+constexpr long long kWideBlocks = 256;
 int rank_split(long long blocks, int rank, bool fp32)
 {
     const long long slots = 2LL * 4 * 256;
+    const int smax = blocks <= kWideBlocks ? 8 : 4;
     int best = 1;
     long long best_cost = -1;
-    for (int S = 1; S <= 4 && S <= (rank > 1 ? rank : 1); ++S) {
+    for (int S = 1; S <= smax && S <= (rank > 1 ? rank : 1); ++S) {
         const long long rounds = (blocks * S + slots - 1) / slots;
         const long long cost = rounds * ((rank + S - 1) / S);
         bool take = best_cost < 0 || cost < best_cost;
@@ -136,19 +142,40 @@ hipError_t launch_t(const AxisLaunch &a, hipStream_t s)
     const int S = G::BLOCK == 64 ? rank_split(blocks, a.rank, sizeof(T) == 4) : 1;
     const size_t lds = ((size_t)S * G::LPB * G::BUF + (tw_mode<T, LOG2L>() == 1 ? G::L : 0)) * sizeof(cpx<T>);
     const dim3 grid((unsigned)blocks), block((unsigned)(G::BLOCK * S));
+    const void *fn;
+    int which;
+    if constexpr (G::BLOCK == 64) {
+        const bool wide = S > 4;
+        which = (wide ? 2 : 0) + (a.forward ? 1 : 0);
+        fn = wide ? (a.forward ? reinterpret_cast<const void *>(&axis_pass<T, LOG2L, 1, 1>)
+                               : reinterpret_cast<const void *>(&axis_pass<T, LOG2L, 0, 1>))
+                  : (a.forward ? reinterpret_cast<const void *>(&axis_pass<T, LOG2L, 1, 0>)
+                               : reinterpret_cast<const void *>(&axis_pass<T, LOG2L, 0, 0>));
+    } else {
+        which = a.forward ? 1 : 0;
+        fn = a.forward ? reinterpret_cast<const void *>(&axis_pass<T, LOG2L, 1, 0>)
+                       : reinterpret_cast<const void *>(&axis_pass<T, LOG2L, 0, 0>);
+    }
     // allow dynamic LDS beyond 64 KB (gfx950 has 160 KB per CU); once per kernel
-    static bool attr_set[2] = {false, false};
-    if (!attr_set[a.forward ? 1 : 0]) {
-        const void *fn = a.forward ? reinterpret_cast<const void *>(&axis_pass<T, LOG2L, 1>)
-                                   : reinterpret_cast<const void *>(&axis_pass<T, LOG2L, 0>);
+    static bool attr_set[4] = {false, false, false, false};
+    if (!attr_set[which]) {
         (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         (void)hipGetLastError();
-        attr_set[a.forward ? 1 : 0] = true;
+        attr_set[which] = true;
+    }
+    if constexpr (G::BLOCK == 64) {
+        if (which >= 2) {
+            if (a.forward)
+                hipLaunchKernelGGL((axis_pass<T, LOG2L, 1, 1>), grid, block, lds, s, a);
+            else
+                hipLaunchKernelGGL((axis_pass<T, LOG2L, 0, 1>), grid, block, lds, s, a);
+            return hipGetLastError();
+        }
     }
     if (a.forward)
-        hipLaunchKernelGGL((axis_pass<T, LOG2L, 1>), grid, block, lds, s, a);
+        hipLaunchKernelGGL((axis_pass<T, LOG2L, 1, 0>), grid, block, lds, s, a);
     else
-        hipLaunchKernelGGL((axis_pass<T, LOG2L, 0>), grid, block, lds, s, a);
+        hipLaunchKernelGGL((axis_pass<T, LOG2L, 0, 0>), grid, block, lds, s, a);
     return hipGetLastError();
 }
 
