@@ -89,15 +89,29 @@ __device__ __forceinline__ void dense_tiles(const AxisLaunch &a, unsigned line0,
         typename M::acc c[RT];
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) c[rt] = zero;
-        for (int k0 = 0; k0 < n; k0 += 4) {
-            const int k = k0 + kl;
-            const bool k_ok = k < n;
-            T bv = 0;
-            if (k_ok && bcol_ok) bv = FWD ? wv[k * n + bcol] : wv[bcol * n + k];
+        // eight k-steps (32 degrees) at a time: their matrix values are
+        // requested together, so the MFMAs wait for one L2 round trip per
+        // eight steps instead of one per step; out-of-range operands load
+        // from a clamped address and are replaced by zero (no branches)
+        constexpr int U = 8;
+        for (int k0 = 0; k0 < n; k0 += 4 * U) {
+            T bv[U];
 #pragma unroll
-            for (int rt = 0; rt < RT; ++rt) {
-                const T av = k_ok ? smem[(rt * 16 + arow) * ld + k] : (T)0;
-                c[rt] = M::step(av, bv, c[rt]);
+            for (int u = 0; u < U; ++u) {
+                const int k = k0 + 4 * u + kl;
+                const bool ok = k < n && bcol_ok;
+                const T w = wv[ok ? (FWD ? k * n + bcol : bcol * n + k) : 0];
+                bv[u] = ok ? w : (T)0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int k = k0 + 4 * u + kl;
+                const bool k_ok = k < n;
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) {
+                    const T a = smem[(rt * 16 + arow) * ld + (k_ok ? k : 0)];
+                    c[rt] = M::step(k_ok ? a : (T)0, bv[u], c[rt]);
+                }
             }
         }
 #pragma unroll
