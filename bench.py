@@ -113,25 +113,27 @@ def time_path(jt, torch, plan, alpha, prec, steps, warmup):
     launches = [(ax, jt.FORWARD, alpha if i == 0 else g, g) for i, ax in enumerate(axes)]
     launches += [(ax, jt.INVERSE, g if i == 0 else back, back) for i, ax in enumerate(axes)]
 
-    def step(record):
-        evs = []
-        if record:
-            e0 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            evs.append(e0)
-        for axis, d, src, dst in launches:
+    def step(evs):
+        if evs:
+            evs[0].record(stream)
+        for i, (axis, d, src, dst) in enumerate(launches):
             plan.apply_axis(axis, d, src, dst, prec=prec, stream=stream)
-            if record:
-                e = torch.cuda.Event(enable_timing=True)
-                e.record(stream)
-                evs.append(e)
+            if evs:
+                evs[i + 1].record(stream)
         return evs
 
+    # every event exists before the timed region (creating them inside it
+    # can stall the queue while the runtime grows its event pool)
+    all_evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(launches) + 1)] for _ in range(steps)]
+    for evs in all_evs:  # torch creates the device event at its first record
+        for e in evs:
+            e.record(stream)
     for _ in range(warmup):
-        step(False)
+        step(None)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    all_evs = [step(True) for _ in range(steps)]
+    for evs in all_evs:
+        step(evs)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     step_ms, launch_ms = [], [[] for _ in launches]
@@ -245,14 +247,15 @@ def workload_1d(args) -> int:
         out = torch.empty_like(alpha)
         for _ in range(args.warmup):
             plan.forward(alpha, out, prec=prec)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        for e0, e1 in evs:  # created at the first record, outside the timed launches
+            e0.record(stream)
+            e1.record(stream)
         torch.cuda.synchronize()
-        evs = []
-        for _ in range(args.steps):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for e0, e1 in evs:
             e0.record(stream)
             plan.forward(alpha, out, prec=prec)
             e1.record(stream)
-            evs.append((e0, e1))
         torch.cuda.synchronize()
         eager = [a.elapsed_time(b) for a, b in evs]
         eager_out = out.cpu().numpy()
@@ -261,14 +264,15 @@ def workload_1d(args) -> int:
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph):
             plan.forward(alpha, gout, prec=prec)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        for e0, e1 in evs:
+            e0.record(stream)
+            e1.record(stream)
         torch.cuda.synchronize()
-        evs = []
-        for _ in range(args.steps):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for e0, e1 in evs:
             e0.record(stream)
             graph.replay()
             e1.record(stream)
-            evs.append((e0, e1))
         torch.cuda.synchronize()
         replay = [a.elapsed_time(b) for a, b in evs]
         assert np.array_equal(gout.cpu().numpy(), eager_out), "graph replay differs from the eager launch"
