@@ -57,7 +57,7 @@ __global__ void __launch_bounds__(WIDE ? 512 : (Geo<LOG2L>::BLOCK == 64 ? 256 : 
     cpx<T> *smem = reinterpret_cast<cpx<T> *>(lds_raw);
     const int S = (int)(blockDim.x / G::BLOCK);
     const cpx<T> *tw = reinterpret_cast<const cpx<T> *>(a.tw);
-    if constexpr (tw_mode<T, LOG2L>() == 1) {
+    if constexpr (tw_mode<T, LOG2L, FWD>() == 1) {
         cpx<T> *tws = smem + S * G::LPB * G::BUF;
         for (int i = (int)threadIdx.x; i < G::L; i += (int)blockDim.x) tws[i] = tw[i];
         __syncthreads();
@@ -140,7 +140,8 @@ hipError_t launch_t(const AxisLaunch &a, hipStream_t s)
     if (blocks <= 0) return hipSuccess;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     const int S = G::BLOCK == 64 ? rank_split(blocks, a.rank, sizeof(T) == 4) : 1;
-    const size_t lds = ((size_t)S * G::LPB * G::BUF + (tw_mode<T, LOG2L>() == 1 ? G::L : 0)) * sizeof(cpx<T>);
+    const int twm = a.forward ? tw_mode<T, LOG2L, 1>() : tw_mode<T, LOG2L, 0>();
+    const size_t lds = ((size_t)S * G::LPB * G::BUF + (twm == 1 ? G::L : 0)) * sizeof(cpx<T>);
     const dim3 grid((unsigned)blocks), block((unsigned)(G::BLOCK * S));
     const void *fn;
     int which;

@@ -235,25 +235,27 @@ struct Geo {
 // the L-entry table when a pass needs them.
 // Where the per-pass twiddles live: 0 = registers (loaded once), 1 = a copy
 // of the table in LDS (loaded once per block), 2 = the table in global memory
-// (L1/L2 resident).  Measured on the 1024-point lines, 2 is fastest in both
-// precisions: registers are better spent on occupancy.
-#ifndef JT_TW_MODE_F32
-#define JT_TW_MODE_F32 2
-#endif
+// (L1/L2 resident).  Measured (one-pass kernel, 1024- and 256-point lines):
+// fp64 is fastest from global memory in both directions; fp32 inverse passes
+// from registers (their direct block leaves registers free at that point);
+// fp32 forward passes from LDS on short lines and from global memory on
+// 1024-point lines.
 #ifndef JT_TW_MODE_F64
 #define JT_TW_MODE_F64 2
 #endif
-template <class T, int LOG2L>
+template <class T, int LOG2L, int FWD>
 constexpr int tw_mode()
 {
     if constexpr (Geo<LOG2L>::BLOCK > 256) return 2;  // big lines: too few registers per lane
-    else return sizeof(T) == 4 ? JT_TW_MODE_F32 : JT_TW_MODE_F64;
+    else if constexpr (sizeof(T) == 8) return JT_TW_MODE_F64;
+    else if constexpr (!FWD) return 0;
+    else return LOG2L <= 8 ? 1 : 2;
 }
 
-template <class T, int LOG2L>
+template <class T, int LOG2L, int FWD>
 struct Twiddles {
     using G = Geo<LOG2L>;
-    static constexpr bool kHoist = tw_mode<T, LOG2L>() == 0;
+    static constexpr bool kHoist = tw_mode<T, LOG2L, FWD>() == 0;
     cpx<T> mid_[(kHoist && G::NMID > 0) ? G::NMID : 1][15];
     cpx<T> fin_[(kHoist && G::RF > 1) ? 16 / G::RF : 1][(G::RF > 1) ? G::RF - 1 : 1];
     const cpx<T> *tw;
@@ -303,9 +305,8 @@ struct Twiddles {
 // line's LDS buffer.  Every thread of the line must call it (it contains the
 // line's barriers); the VL lanes of a thread are processed between the same
 // barriers.
-template <class T, int LOG2L, int VL>
-__device__ __forceinline__ void fft_line(cpx<T> (*v)[16], cpx<T> *buf, const int *pv,
-                                         const Twiddles<T, LOG2L> *tw)
+template <class T, int LOG2L, int VL, class TW>
+__device__ __forceinline__ void fft_line(cpx<T> (*v)[16], cpx<T> *buf, const int *pv, const TW *tw)
 {
     using G = Geo<LOG2L, VL>;
     static_assert(G::L >= 64, "lines shorter than 64 use the dense path with L = 64");
@@ -399,7 +400,7 @@ __device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, 
     const cpx<T> *vf = reinterpret_cast<const cpx<T> *>(a.v);
     const T *wv = reinterpret_cast<const T *>(a.wv);
 
-    Twiddles<T, LOG2L> twd[VL];
+    Twiddles<T, LOG2L, FWD> twd[VL];
 #pragma unroll
     for (int h = 0; h < VL; ++h) twd[h].load(tw, pv[h]);
 
@@ -486,7 +487,8 @@ __device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, 
 #ifndef JT_HOIST_F64
 #define JT_HOIST_F64 1
 #endif
-        constexpr bool kHB = JT_HOIST_BINS && Geo<LOG2L>::BLOCK <= 256 && (sizeof(T) == 4 || JT_HOIST_F64);
+        // (fp64 only from 512 points: measured slower on 256-point lines)
+        constexpr bool kHB = JT_HOIST_BINS && Geo<LOG2L>::BLOCK <= 256 && (sizeof(T) == 4 || (JT_HOIST_F64 && LOG2L >= 9));
         int bix[VL][kHB ? 16 : 1];
         if constexpr (kHB) {
 #pragma unroll
