@@ -665,10 +665,9 @@ __device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, 
         // the nodes of each owned bin m (at most two in almost every plan), as
         // padded LDS slots packed j_a | j_b << 16 (0xffff: none); the same for
         // every term, so they are read once
-#ifndef JT_BPAIR_F64
-#define JT_BPAIR_F64 0
-#endif
-        constexpr bool kBP = Geo<LOG2L>::BLOCK <= 256 && (sizeof(T) == 4 || JT_BPAIR_F64);
+        // (fp64 only up to 256 points: measured faster there, much slower
+        // on 1024-point lines, where the registers are short)
+        constexpr bool kBP = Geo<LOG2L>::BLOCK <= 256 && (sizeof(T) == 4 || LOG2L <= 8);
         const bool two = kBP && a.max_per_bin <= 2;
         unsigned bpair[VL][kBP ? 16 : 1];
 #pragma unroll
