@@ -17,6 +17,19 @@ Section 3.3 eqs. (56)-(60)):
 
 The apply step is a plain matrix product along each axis (numpy, fp64), with
 no blocking, reordering or fusion beyond that.
+
+Two more routines of the same C file serve checks the long-double build is
+too slow for, and the nonuniform transform:
+
+* ``apply1d_fp64`` / ``nodes_fp64``: the same 1D definition in plain fp64
+  (nodes isolated by sign changes of phat_n on a grid in t and refined by
+  safeguarded Newton; Christoffel weights; the sums by the recurrence, no
+  matrix stored).  For checking fp32-bulk results of long 1D items.
+* ``ptilde`` / ``forward_points``: the modified Jacobi functions
+  Ptilde_k(t) = phat_k(cos t) sqrt(w(cos t) sin t) at given angles, and the
+  nonuniform forward transform f = (P0 (x) P1 (x) ...) alpha with
+  P_i[j, k] = Ptilde_k(t_{i,j}) (Section 3.1, the nonuniform remark after
+  eq. (39); Sections 3.2-3.3 for 2D/3D), no quadrature weights.
 """
 from __future__ import annotations
 
@@ -37,7 +50,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle's C part (gcc, OpenMP).  Returns the library path."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"]
+        cmd = ["gcc", "-O3", "-fopenmp", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"]
         subprocess.check_call(cmd)
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -54,6 +67,12 @@ def _load():
         lib.orc_build.restype = ctypes.c_int
         lib.orc_recurrence.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp, dp]
         lib.orc_recurrence.restype = ctypes.c_int
+        lib.orc_ptilde.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, dp]
+        lib.orc_ptilde.restype = ctypes.c_int
+        lib.orc_nodes_fp64.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp]
+        lib.orc_nodes_fp64.restype = ctypes.c_int
+        lib.orc_apply_fp64.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, dp]
+        lib.orc_apply_fp64.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -141,3 +160,47 @@ def _entries(x, params, index, transpose):
             t = t @ mats[axis][idx[axis]]
         out[s] = t
     return out
+
+
+# ------------------------------------------------------------------ plain fp64 1D path
+def nodes_fp64(n: int, a: float, b: float):
+    """(x, omega) in fp64: nodes descending in x (ascending in t), Christoffel weights."""
+    x = np.empty(n)
+    w = np.empty(n)
+    rc = _load().orc_nodes_fp64(int(n), float(a), float(b), _ptr(x), _ptr(w))
+    if rc != 0:
+        raise ValueError("oracle: node search failed (code %d) for n=%r a=%r b=%r" % (rc, n, a, b))
+    return x, w
+
+
+def apply1d_fp64(v: np.ndarray, ab, transpose: bool = False) -> np.ndarray:
+    """A v (transpose=False) or A^T v for one 1D axis, in plain fp64."""
+    v = np.ascontiguousarray(v, dtype=np.float64).ravel()
+    y = np.empty_like(v)
+    rc = _load().orc_apply_fp64(len(v), float(ab[0]), float(ab[1]), 1 if transpose else 0, _ptr(v), _ptr(y))
+    if rc != 0:
+        raise ValueError("oracle: fp64 apply failed (code %d)" % rc)
+    return y
+
+
+# ------------------------------------------------------------------ nonuniform transform
+def ptilde(n: int, a: float, b: float, t) -> np.ndarray:
+    """P[j, k] = Ptilde_k(t_j) for k < n at the given angles t_j in (0, pi)."""
+    t = np.ascontiguousarray(t, dtype=np.float64).ravel()
+    out = np.empty((len(t), n))
+    rc = _load().orc_ptilde(int(n), float(a), float(b), len(t), _ptr(t), _ptr(out))
+    if rc != 0:
+        raise ValueError("oracle: bad arguments to ptilde (code %d)" % rc)
+    return out
+
+
+def forward_points(alpha: np.ndarray, params, points) -> np.ndarray:
+    """Nonuniform forward transform: along axis i apply P_i[j, k] = Ptilde_k(t_{i,j})
+    (points[i] = the angles of axis i); no quadrature weights."""
+    x = np.asarray(alpha, dtype=np.float64)
+    if x.ndim != len(params) or len(points) != x.ndim:
+        raise ValueError("need one (a, b) pair and one point set per axis")
+    for axis, ((a, b), t) in enumerate(zip(params, points)):
+        P = ptilde(x.shape[axis], a, b, t)
+        x = np.moveaxis(np.tensordot(P, x, axes=([1], [axis])), 0, axis)
+    return np.ascontiguousarray(x)

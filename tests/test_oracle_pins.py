@@ -213,3 +213,118 @@ def test_rejects_invalid_parameters(orc):
         orc.matrix(8, -1.0, 0.0)
     with pytest.raises(ValueError):
         orc.matrix(0, 0.0, 0.0)
+
+
+# ------------------------------------------------- modified Jacobi functions (nonuniform)
+# Closed forms of Ptilde_k(t) = phat_k(cos t) sqrt(w(cos t) sin t) at the four
+# Chebyshev parameter pairs (first to fourth kind): each normalised on (0, pi)
+# and positive at t -> 0+ where the polynomial is positive at x = 1.
+_PTILDE_CLOSED = {
+    (-0.5, -0.5): lambda k, t: np.where(k == 0, np.sqrt(1 / np.pi), np.sqrt(2 / np.pi) * np.cos(k * t)),
+    (0.5, 0.5): lambda k, t: np.sqrt(2 / np.pi) * np.sin((k + 1) * t),
+    (-0.5, 0.5): lambda k, t: np.sqrt(2 / np.pi) * np.cos((k + 0.5) * t),
+    (0.5, -0.5): lambda k, t: np.sqrt(2 / np.pi) * np.sin((k + 0.5) * t),
+}
+
+
+@pytest.mark.parametrize("ab", list(_PTILDE_CLOSED))
+def test_ptilde_chebyshev_closed_forms(orc, ab):
+    n = 300
+    t = np.sort(np.random.default_rng(21).uniform(1e-3, np.pi - 1e-3, 97))
+    P = orc.ptilde(n, ab[0], ab[1], t)
+    k = np.arange(n)[None, :]
+    ref = _PTILDE_CLOSED[ab](k, t[:, None])
+    assert np.abs(P - ref).max() <= 1e-13
+
+
+def test_ptilde_swapped_parameters_fail_the_pin(orc):
+    """Planted mistake: (a, b) swapped in the call gives the other kind."""
+    t = np.linspace(0.1, 3.0, 11)
+    P = orc.ptilde(20, 0.5, -0.5, t)
+    ref = _PTILDE_CLOSED[(-0.5, 0.5)](np.arange(20)[None, :], t[:, None])
+    assert np.abs(P - ref).max() > 0.1
+
+
+@pytest.mark.parametrize("a,b", [(0.25, -0.35), (-0.8, 0.6), (0.9, 0.3)])
+def test_ptilde_mpmath_definition(orc, a, b):
+    """The paper's definition of the modified Jacobi function of the first
+    kind (Section 1): C_k P_k^(a,b)(cos t) sin(t/2)^(a+1/2) cos(t/2)^(b+1/2)
+    with C_k = sqrt((2k+a+b+1) Gamma(1+k) Gamma(1+k+a+b) / (Gamma(1+k+a) Gamma(1+k+b))),
+    P_k from mpmath's own Jacobi function, at 30 digits."""
+    n = 14
+    t = [0.05, 0.7, 1.5, 2.2, 3.1]
+    P = orc.ptilde(n, a, b, np.array(t))
+    with mp.workdps(30):
+        for j, tj in enumerate(t):
+            for k in range(n):
+                c = mp.sqrt((2 * k + a + b + 1) * mp.gamma(1 + k) * mp.gamma(1 + k + a + b)
+                            / (mp.gamma(1 + k + a) * mp.gamma(1 + k + b)))
+                ref = c * mp.jacobi(k, a, b, mp.cos(tj)) * mp.sin(mp.mpf(tj) / 2) ** (a + 0.5) \
+                    * mp.cos(mp.mpf(tj) / 2) ** (b + 0.5)
+                assert abs(P[j, k] - float(ref)) <= 1e-13 * max(1.0, abs(float(ref))), (j, k)
+
+
+def test_ptilde_at_gauss_jacobi_nodes_weighted_is_the_uniform_matrix(orc):
+    """sqrt(w_j) Ptilde_k(t_j) with the trigonometric weights of eq. (9) is the
+    uniform matrix W J (the uniform transform is the nonuniform one at the
+    quadrature nodes, with the weights applied)."""
+    n, a, b = 200, 0.3, -0.45
+    A, x, om = orc.matrix(n, a, b)
+    t = np.arccos(x)
+    w_trig = om / ((1 - x) ** a * (1 + x) ** b * np.sin(t))
+    P = orc.ptilde(n, a, b, t)
+    assert np.abs(np.sqrt(w_trig)[:, None] * P - A).max() <= 1e-12
+
+
+def test_forward_points_kronecker_convention(orc):
+    """2D nonuniform forward: f[i, j] = sum_{k,l} alpha[k, l] Ptilde_k(s_i) Ptilde_l(t_j)."""
+    rng = np.random.default_rng(5)
+    al = rng.standard_normal((7, 9))
+    s, t = rng.uniform(0.1, 3.0, 7), rng.uniform(0.1, 3.0, 9)
+    ab = ((0.2, -0.1), (-0.3, 0.4))
+    P0, P1 = orc.ptilde(7, *ab[0], s), orc.ptilde(9, *ab[1], t)
+    ref = np.kron(P0, P1) @ al.ravel()
+    assert np.abs(orc.forward_points(al, ab, (s, t)).ravel() - ref).max() <= 1e-13
+
+
+# ------------------------------------------------- plain fp64 path (long 1D items)
+@pytest.mark.parametrize("n", [1, 5, 64, 65, 4096])
+def test_fp64_path_chebyshev_closed_forms(orc, n):
+    """Nodes and transforms at a = b = -1/2 (DCT-III / DCT-II) and a = b = 1/2
+    (DST-I).  The bound grows like n^2 * 4e-16: the nodes next to x = +-1 are
+    held in fp64 x, and phat_k for k ~ n turns an error of one unit in the
+    last place of x into about n^2 * 1e-16 there (a limit of the fp64 path,
+    far below the fp32-bulk bar it serves)."""
+    tol = max(1e-12, 4e-16 * n * n)
+    j = np.arange(1, n + 1)
+    x, w = orc.nodes_fp64(n, -0.5, -0.5)
+    np.testing.assert_allclose(x, np.cos((2 * j - 1) * np.pi / (2 * n)), rtol=0, atol=4e-15)
+    v = np.random.default_rng(n).standard_normal(n)
+    ref = scipy.fft.dct(v, type=3, norm="ortho")
+    assert np.abs(orc.apply1d_fp64(v, (-0.5, -0.5)) - ref).max() <= tol * max(1.0, np.abs(ref).max())
+    assert np.abs(orc.apply1d_fp64(v, (-0.5, -0.5), True) - scipy.fft.dct(v, type=2, norm="ortho")).max() <= tol
+    x, w = orc.nodes_fp64(n, 0.5, 0.5)
+    np.testing.assert_allclose(x, np.cos(j * np.pi / (n + 1)), rtol=0, atol=4e-15)
+    assert np.abs(orc.apply1d_fp64(v, (0.5, 0.5)) - scipy.fft.dst(v, type=1, norm="ortho")).max() <= tol
+
+
+@pytest.mark.parametrize("n,a,b", [(64, 0.25, -0.35), (1000, -0.9, 0.8), (4096, 0.4, 0.1)])
+def test_fp64_path_matches_long_double_build(orc, n, a, b):
+    """Against the long-double construction (itself pinned above): nodes and the
+    transform in both directions."""
+    A, x, om = orc.matrix(n, a, b)
+    xf, wf = orc.nodes_fp64(n, a, b)
+    assert np.abs(xf - x).max() <= 1e-14
+    v = np.random.default_rng(3).standard_normal(n)
+    assert np.linalg.norm(orc.apply1d_fp64(v, (a, b)) - A @ v) <= 1e-10 * np.linalg.norm(v)
+    assert np.linalg.norm(orc.apply1d_fp64(v, (a, b), True) - A.T @ v) <= 1e-10 * np.linalg.norm(v)
+
+
+def test_fp64_path_orthogonal_at_the_largest_size(orc):
+    """At n = 16384 (the longest 1D item): the map is orthogonal, so the
+    round trip returns v and the norm is kept."""
+    n, ab = 16384, (-0.35, 0.45)
+    v = np.random.default_rng(4).standard_normal(n)
+    g = orc.apply1d_fp64(v, ab)
+    assert abs(np.linalg.norm(g) / np.linalg.norm(v) - 1) <= 1e-10
+    assert np.linalg.norm(orc.apply1d_fp64(g, ab, True) - v) <= 1e-9 * np.linalg.norm(v)
