@@ -67,7 +67,8 @@ typedef enum { JT_FORWARD = 0, JT_INVERSE = 1 } jt_direction;
 
 /* Optional planning knobs; jt_plan() uses the defaults listed here. */
 typedef struct {
-    int nu0;          /* width of the direct (low-degree) block; default 27 (Section 3.1) */
+    int nu0;          /* width of the direct (low-degree) block; default 27 (Section 3.1);
+                         at most 64 (JT_EINVAL above) */
     int dense_below;  /* n below this (and at most 1024) keeps the whole matrix: the dense
                          matrix-core pass, no FFT terms; default 64 */
     int oversample;   /* q of Algorithm 2.1; default 2 */
@@ -118,7 +119,13 @@ jt_status jt_plan_dims(jt_plan_t plan, int *d);
 jt_status jt_plan_info(jt_plan_t plan, int axis, jt_axis_info *info);
 
 /* Copy the axis' nodes t_j (ascending), x_j = cos t_j and Gauss-Jacobi weights
- * omega_j into caller host arrays of length n.  Any pointer may be NULL. */
+ * omega_j into caller host arrays of length n.  Any pointer may be NULL.
+ * The nodes are the n zeros of the degree-n Jacobi polynomial for the weight
+ * (1-x)^a (1+x)^b and omega_j the weights of the n-point Gauss-Jacobi rule
+ * (Section 2, eq. (2); Section 3.1, eq. (35)), in the order of ascending
+ * t_j = arccos x_j; the trigonometric weights of eq. (9) are
+ * w_j = omega_j / ((1-x_j)^a (1+x_j)^b sin t_j).
+ * Errors: JT_EINVAL (null plan or axis out of range). */
 jt_status jt_plan_nodes(jt_plan_t plan, int axis, double *t, double *x, double *omega);
 
 /* Copy the axis' factors to caller host arrays (any pointer may be NULL):
@@ -139,9 +146,11 @@ jt_status jt_plan_entries(jt_plan_t plan, int axis, int count, const int *rows, 
 jt_status jt_plan_device_bytes(jt_plan_t plan, size_t *bytes);
 
 /* Copy the packed factors into the caller's device buffer dev_buf (at least
- * jt_plan_device_bytes bytes, 256-byte aligned) with one asynchronous copy on
- * `stream` (a hipStream_t; NULL = default stream).  The plan keeps the pointer;
- * the buffer must stay allocated and unmodified while the plan is used.
+ * jt_plan_device_bytes bytes, 256-byte aligned) with one copy enqueued on
+ * `stream` (a hipStream_t; NULL = default stream), then wait for that stream
+ * (the copy reads the plan's host image), so the call returns with the
+ * stream drained.  The plan keeps the pointer; the buffer must stay
+ * allocated and unmodified while the plan is used.
  * Errors: JT_EINVAL, JT_ENOMEM (buffer too small), JT_EDEVICE. */
 jt_status jt_plan_bind(jt_plan_t plan, void *dev_buf, size_t bytes, void *stream);
 
@@ -155,7 +164,12 @@ jt_status jt_plan_pack(jt_plan_t plan, void *host_dst, size_t bytes);
 jt_status jt_workspace_bytes(jt_plan_t plan, jt_prec prec, size_t *bytes);
 
 /*
- * Forward transform g = (W0 J0 (x) ... ) alpha on device buffers.
+ * Forward transform g = (W0 J0 (x) ... ) alpha on device buffers: the
+ * uniform forward Jacobi transform of Section 3.1 (eqs. (35)-(39): g_j =
+ * sqrt(w_j) sum_k alpha_k Ptilde_k(t_j), the values of the expansion at the
+ * Gauss-Jacobi nodes weighted by the square roots of the quadrature weights),
+ * computed per line as eq. (50), and along every axis for d = 2, 3
+ * (Section 3.2, eq. (54); Section 3.3, eq. (59)).
  *   alpha_dev : input, prod n[i] elements of dtype `in`
  *   g_dev     : output, prod n[i] elements of dtype `out`; may equal alpha_dev
  *               only when in == out
@@ -168,8 +182,10 @@ jt_status jt_workspace_bytes(jt_plan_t plan, jt_prec prec, size_t *bytes);
 jt_status jt_forward(jt_plan_t plan, const void *alpha_dev, jt_dtype in, void *g_dev, jt_dtype out,
                      jt_prec prec, void *stream);
 
-/* Inverse transform alpha = (W0 J0 (x) ... )^T g (eqs. (51), (55), (60)); same
- * argument rules as jt_forward. */
+/* Inverse transform alpha = (W0 J0 (x) ... )^T g on device buffers: the
+ * transpose of the forward map, which is its inverse because W J is
+ * orthogonal (Section 3.1: eq. (51) per line; Section 3.2, eq. (55);
+ * Section 3.3, eq. (60)).  Same argument rules and errors as jt_forward. */
 jt_status jt_inverse(jt_plan_t plan, const void *g_dev, jt_dtype in, void *alpha_dev, jt_dtype out,
                      jt_prec prec, void *stream);
 

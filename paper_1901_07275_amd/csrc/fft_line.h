@@ -592,16 +592,25 @@ __device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, 
 #pragma unroll
             for (int q = 0; q < 16; ++q) acc[h][q] = 0.0;
         constexpr int KC = Geo<LOG2L>::BLOCK <= 256 ? 8 : 2;  // fewer live sums on register-poor long lines
-        double *red = reinterpret_cast<double *>(buf);  // free until the first term
         const int nchunks = (nu0 + KC - 1) / KC;
         const int rounds = (nchunks + S - 1) / S;
-        // When n is a multiple of 4 the line is staged in LDS (behind the
-        // sums in red) and each thread takes groups of four consecutive
-        // nodes, so a degree's row of WV is read with 16-byte loads: the
-        // block re-reads WV for every line, and four times fewer (wider)
-        // loads is what this block's time depends on.
-        const bool vec4 = (n & 3) == 0;  // uniform
-        T *gs = reinterpret_cast<T *>(reinterpret_cast<unsigned char *>(buf) + (G::TPL > 64 ? 1024 : 256));
+        // The line buffer is free until the first term.  It holds, in order:
+        // the per-degree sums red[0, nu0) (rounded up to 16 bytes), the
+        // per-wave partials of line_sum (lines over several waves), and the
+        // staged line gs.  The host caps nu0 at 64, so red and the partials
+        // always fit (512 + 256 bytes against at least 544 bytes of buffer).
+        // When n is a multiple of 4 and the staged line fits behind them, each
+        // thread takes groups of four consecutive nodes, so a degree's row of
+        // WV is read with 16-byte loads: the block re-reads WV for every line,
+        // and four times fewer (wider) loads is what this block's time depends
+        // on.  Otherwise the lanes sum over the nodes they own.
+        double *red = reinterpret_cast<double *>(buf);
+        const int red_n = (nu0 + 1) & ~1;
+        constexpr int LSUM = G::TPL > 64 ? (G::TPL / 64) * KC : 0;
+        double *lsum = red + red_n;
+        const int gs_off = 8 * (red_n + LSUM);  // bytes; a multiple of 16
+        const bool vec4 = (n & 3) == 0 && gs_off + G::L * (int)sizeof(T) <= G::BUF * (int)sizeof(cpx<T>);  // uniform
+        T *gs = reinterpret_cast<T *>(reinterpret_cast<unsigned char *>(buf) + gs_off);
         if (vec4) {
 #pragma unroll
             for (int h = 0; h < VL; ++h)
@@ -648,7 +657,7 @@ __device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, 
                         }
                     }
             }
-            line_sum<G::TPL, KC>(part, red + 64, tid % G::TPL);
+            line_sum<G::TPL, KC>(part, lsum, tid % G::TPL);
             if (ch < nchunks && tid % G::TPL == 0)
 #pragma unroll
                 for (int c = 0; c < KC; ++c)

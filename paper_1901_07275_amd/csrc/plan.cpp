@@ -667,6 +667,7 @@ void build_axis(AxisPlan &ax, int n, double a, double b, double tol, const PlanO
     if (!(a > -1.0) || !(b > -1.0) || !(a < 1.0) || !(b < 1.0))
         throw std::invalid_argument("a and b must lie in (-1, 1)");
     if (!(tol >= 1e-14) || !(tol <= 1e-2)) throw std::invalid_argument("tol must lie in [1e-14, 1e-2]");
+    if (opt.nu0 < 1 || opt.nu0 > kMaxNu0) throw std::invalid_argument("nu0 must lie in [1, 64]");
     ax = AxisPlan();
     ax.n = n; ax.a = a; ax.b = b; ax.tol = tol;
     int L = 64;

@@ -44,8 +44,12 @@ struct AxisPlan {
     size_t bytes = 0;
 };
 
+// Widest direct block an FFT-path axis may have: the axis pass keeps the
+// inverse direct block's per-degree sums at the front of a line buffer.
+constexpr int kMaxNu0 = 64;
+
 struct PlanOptions {
-    int nu0 = 27;           // Section 3.1 uses 27
+    int nu0 = 27;           // Section 3.1 uses 27; at most kMaxNu0
     int dense_below = 64;   // n < dense_below: the direct block covers all degrees
     int oversample = 2;     // q in Algorithm 2.1
     int iterations = 2;     // repetitions of steps 2-3 (Section 2.1 uses two)

@@ -157,6 +157,10 @@ struct Flight {
     std::vector<unsigned char> image;  // host copy of the launch's tables (alive until the copy is done)
     size_t table_off = 0;
     hipEvent_t done = nullptr;         // outputs copied back
+    // the launch's error word (bit 0: a wait for a previous pass timed out,
+    // bit 1: unsupported length), copied back with the outputs; on the heap
+    // so that its address survives moving the flight into the queue
+    std::unique_ptr<uint32_t> err_word{new uint32_t(0)};
     double coeffs = 0;
 };
 
@@ -347,13 +351,18 @@ struct jt_server_s {
             Flight &f = flights.front();
             if (hipEventQuery(f.done) != hipSuccess) break;
             const double t = now_s();
+            const bool bad = *f.err_word != 0;
             for (Request *r : f.reqs) {
+                release_request(r);
+                if (bad) {
+                    fail_request(r, JT_EDEVICE);
+                    continue;
+                }
                 r->state = kDone;
                 r->t_done = t;
-                release_request(r);
                 st.completed++;
             }
-            st.coeffs += f.coeffs;
+            if (!bad) st.coeffs += f.coeffs;
             arena.release(f.table_off, f.image.size());
             (void)hipEventDestroy(f.done);
             flights.pop_front();
@@ -556,6 +565,8 @@ struct jt_server_s {
         for (Request *r : take)
             if (e == hipSuccess)
                 e = hipMemcpyAsync(r->hout, arena_ptr + r->out_off, r->out_bytes, hipMemcpyDeviceToHost, s_out);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(f.err_word.get(), b.counters + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s_out);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&f.done, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventRecord(f.done, s_out);
         // the events above only order the streams; the flight's own event marks completion

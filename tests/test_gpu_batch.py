@@ -1,8 +1,8 @@
 """GPU parity of the batched form: many independent transforms of uneven n,
 d and (a, b) in one persistent launch, against the oracle item by item.
 
-Tolerances as in the single-transform tests: fp32-bulk 2e-5 rel-l2 (plus
-20 tol d), fp64 1e-11 at tol 1e-12.  A graph replay must equal the eager run
+Tolerances as in the single-transform tests: fp32-bulk (tol 1e-7) 2e-5
+rel-l2, fp64 1e-11 at tol 1e-12, per item in every dimension.  A graph replay must equal the eager run
 bit for bit (the arithmetic of a unit does not depend on which block runs it).
 """
 import numpy as np
@@ -89,7 +89,7 @@ def test_batch_mixed_items(jt, orc, prec, tol):
     torch.cuda.synchronize()
     assert P.batch.errors() == 0
     floor = 1e-11 if prec == 0 else 2e-5
-    w = _check_items(jt, orc, P, P.out.cpu().numpy(), lambda d: floor + 20 * tol * d)
+    w = _check_items(jt, orc, P, P.out.cpu().numpy(), lambda d: floor)
     print("worst item rel-l2 %.3e" % w)
 
 
@@ -100,7 +100,7 @@ def test_batch_dtypes(jt, orc, tin_name, tout_name):
     P.batch.run(P.inp, P.out)
     torch.cuda.synchronize()
     assert P.batch.errors() == 0
-    _check_items(jt, orc, P, P.out.cpu().numpy(), lambda d: 2e-5 + 20e-7 * d)
+    _check_items(jt, orc, P, P.out.cpu().numpy(), lambda d: 2e-5)
 
 
 @pytest.mark.parametrize("opts", [{"max_split": 1}, {"min_units": 8}, {"grid": 3}])
@@ -109,7 +109,7 @@ def test_batch_tiling_options_give_the_same_results(jt, orc, opts):
     P.batch.run(P.inp, P.out)
     torch.cuda.synchronize()
     assert P.batch.errors() == 0
-    _check_items(jt, orc, P, P.out.cpu().numpy(), lambda d: 2e-5 + 20e-7 * d)
+    _check_items(jt, orc, P, P.out.cpu().numpy(), lambda d: 2e-5)
 
 
 def test_batch_matches_the_single_transform_path(jt):
@@ -132,7 +132,7 @@ def test_batch_in_place(jt, orc):
     buf = P.inp.clone()
     P.batch.run(buf, buf)
     torch.cuda.synchronize()
-    _check_items(jt, orc, P, buf.cpu().numpy(), lambda d: 2e-5 + 20e-7 * d)
+    _check_items(jt, orc, P, buf.cpu().numpy(), lambda d: 2e-5)
     assert dev.type == "cuda"
 
 
@@ -157,10 +157,10 @@ def test_batch_graph_replay_matches_eager(jt):
 
 def test_batch_ragged_1d_sample(jt, orc):
     """Items drawn like the 4096-item ragged 1D workload (n log-uniform in
-    [64, 16384], (a, b) uniform in (-0.5, 0.5)), fp32 bulk, tol 1e-7; items
-    up to n = 4096 are checked whole against the oracle, three longer ones
-    (shortest, median, longest) on 64 sampled outputs each; every item also
-    passes through the round-trip test below."""
+    [64, 16384], (a, b) uniform in (-0.5, 0.5)), fp32 bulk, tol 1e-7, every
+    item checked whole: against the long-double oracle up to n = 4096 and
+    against its plain fp64 path above (the full 4096-item batch is checked in
+    test_gpu_full_batch.py)."""
     items = workloads.batch_1d(48, seed=104)
     shapes = [(n,) for n, _, _ in items]
     abs_ = [(ab,) for _, ab, _ in items]
@@ -172,20 +172,11 @@ def test_batch_ragged_1d_sample(jt, orc):
     torch.cuda.synchronize()
     assert P.batch.errors() == 0
     out = P.out.cpu().numpy()
-    rng = np.random.default_rng(7)
-    large = sorted((n, i) for i, (n, _, _) in enumerate(items) if n > 4096)
-    sampled = {large[0][1], large[len(large) // 2][1], large[-1][1]} if large else set()
     for i, (n, ab, x) in enumerate(items):
         got = P.item(out, i)
-        if n <= 4096:
-            ref = orc.forward(x, (ab,))
-            assert relerr(got, ref) <= 2e-5 + 20e-7, (i, n)
-        elif i in sampled:
-            idx = rng.integers(0, n, size=(64, 1))
-            ref = orc.forward_entries(x, (ab,), idx)
-            scale = np.linalg.norm(x)  # |g| = |x| (orthogonal), entries are O(|x| / sqrt(n))
-            assert np.abs(got[idx[:, 0]] - ref).max() <= 2e-5 * scale, (i, n)
-            orc.clear_cache()
+        ref = orc.forward(x, (ab,)) if n <= 4096 else orc.apply1d_fp64(x, ab)
+        assert relerr(got, ref) <= 2e-5, (i, n)
+    orc.clear_cache()
 
 
 def test_batch_ragged_2d_sample(jt, orc):
@@ -200,7 +191,7 @@ def test_batch_ragged_2d_sample(jt, orc):
     P.batch.run(P.inp, P.out)
     torch.cuda.synchronize()
     assert P.batch.errors() == 0
-    _check_items(jt, orc, P, P.out.cpu().numpy(), lambda d: 2e-5 + 20e-7 * d)
+    _check_items(jt, orc, P, P.out.cpu().numpy(), lambda d: 2e-5)
 
 
 def test_batch_round_trip_property(jt):

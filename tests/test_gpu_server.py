@@ -1,6 +1,6 @@
 """GPU tests of the serving form (continuous batching over a device arena).
 
-Each result must match the oracle (fp32 bulk: 2e-5 + 20 tol d rel-l2), and
+Each result must match the oracle (fp32 bulk at tol 1e-7: 2e-5 rel-l2), and
 must be bit-for-bit the same whether the request ran alone or in a mix: a
 unit's arithmetic does not depend on the other requests of its launch.
 """
@@ -57,7 +57,7 @@ def test_server_alone_matches_oracle_and_mix_is_bitwise_equal(jt, orc):
         assert info["state"] == 3
         e = relerr(out, _oracle(orc, x, ab, d))
         print("alone", s, "rel-l2 %.2e" % e, "cold", info["cold"], flush=True)
-        assert e <= 2e-5 + 20e-7 * len(s)
+        assert e <= 2e-5
         alone.append(out.copy())
     st = S.stats()
     assert st["completed"] == len(REQS) and st["failed"] == 0
@@ -98,7 +98,7 @@ def test_server_admission_in_a_small_arena(jt, orc):
     assert st["failed"] == 0
     for i, out in outs:
         s, ab, d = REQS[i]
-        assert relerr(out, _oracle(orc, xs[i], ab, d)) <= 2e-5 + 20e-7 * len(s)
+        assert relerr(out, _oracle(orc, xs[i], ab, d)) <= 2e-5
     S.close()
 
 
@@ -161,11 +161,20 @@ def test_server_mixed_stream_sample(jt, orc):
         tickets.append(S.submit(x, out, ab, direction))
     infos = [S.wait(t) for t in tickets]
     assert all(inf["state"] == 3 for inf in infos)
-    for (d, s, ab, direction), x, out in zip(reqs, xs, outs):
+    big = 0
+    for k, ((d, s, ab, direction), x, out) in enumerate(zip(reqs, xs, outs)):
         if int(np.prod(s)) <= 1 << 20:
-            assert relerr(out, _oracle(orc, x, ab, direction)) <= 2e-5 + 20e-7 * d
-        else:  # orthogonality: the norm is kept
+            assert relerr(out, _oracle(orc, x, ab, direction)) <= 2e-5
+        else:
+            # 256 outputs, each computed on its own by the oracle; their
+            # rel-l2 against the sample's norm (entries are O(|x| / sqrt(N)))
+            big += 1
+            idx = np.random.default_rng(k).integers(0, np.array(s), size=(256, len(s)))
+            f = orc.forward_entries if direction == 0 else orc.inverse_entries
+            ref = f(x.astype(np.float64), ab, idx)
+            assert relerr(out[tuple(idx.T)].astype(np.float64), ref) <= 2e-5, (k, s)
             assert abs(np.linalg.norm(out) / np.linalg.norm(x) - 1) <= 1e-4
+    print("requests above 2^20 coefficients checked on samples: %d" % big)
     st = S.stats()
     print("stream stats", st, flush=True)
     S.close()
@@ -183,7 +192,7 @@ def test_server_dense_crossover_per_regime(jt, orc):
         x = rng.standard_normal(s).astype(np.float32)
         out = np.full(s, np.nan, np.float32)
         S.wait(S.submit(x, out, ab))
-        assert relerr(out, _oracle(orc, x, ab, 0)) <= 2e-5 + 20e-7 * len(s)
+        assert relerr(out, _oracle(orc, x, ab, 0)) <= 2e-5
     st = S.stats()
     # n = 200 twice (FFT for the 1D request, dense for the 2D one) and n = 40
     assert st["plans_cached"] == 3 and st["plan_misses"] == 3
