@@ -263,6 +263,19 @@ jt_status jt_batch_bind(jt_batch_t batch, void *dev_buf, size_t bytes, void *str
 /* Run every item: one counter-clearing kernel and the persistent kernel on
  * `stream`, no host synchronisation.  Runs of one batch must not overlap. */
 jt_status jt_batch_run(jt_batch_t batch, const void *in_base, void *out_base, void *stream);
+/* As jt_batch_run, for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the run's counters (queue head, error word, done-units per pass) live in an
+ * array the library keeps in each device's memory (256 KiB, 65536 words, held
+ * until the process ends) instead of the batch's bound buffer, and the call
+ * allocates nothing.  The batch must still be bound (its unit and pass
+ * tables stay in the bound buffer).  The run's error word is copied to the
+ * batch's own slot afterwards, so jt_batch_errors reads it as usual.  Every
+ * call on one device shares that array: calls (and jt_batch_run_static runs
+ * of different batches) must not overlap on one device; they race.
+ * Errors: JT_EINVAL (more than 65534 axis passes, null argument, in-place
+ * with unequal dtypes), JT_ESTATE (not bound), JT_EDEVICE. */
+jt_status jt_batch_run_static(jt_batch_t batch, const void *in_base, void *out_base, void *stream);
 /* Capture jt_batch_run(in_base, out_base) into a HIP graph held by the batch
  * (replaces an earlier capture); jt_batch_replay launches it on `stream`. */
 jt_status jt_batch_capture(jt_batch_t batch, const void *in_base, void *out_base);

@@ -125,6 +125,7 @@ SYMBOLS = {
     "jt_batch_device_bytes": [_vp, ctypes.POINTER(ctypes.c_size_t)],
     "jt_batch_bind": [_vp, _vp, ctypes.c_size_t, _vp],
     "jt_batch_run": [_vp, _vp, _vp, _vp],
+    "jt_batch_run_static": [_vp, _vp, _vp, _vp],
     "jt_batch_capture": [_vp, _vp, _vp],
     "jt_batch_replay": [_vp, _vp],
     "jt_batch_errors": [_vp, _vp, ctypes.POINTER(ctypes.c_uint32)],
@@ -456,6 +457,16 @@ class Batch:
         i, o = self._bufs(inp, out)
         st = stream if stream is not None else torch.cuda.current_stream(inp.device)
         _check(_lib.jt_batch_run(self._h, i, o, _vp(st.cuda_stream)))
+        return out
+
+    def run_static(self, inp, out, stream=None):
+        """As run(), with the run's counters in the library's own device array
+        (jt_batch_run_static: allocates nothing; runs on one device must not overlap)."""
+        import torch
+
+        i, o = self._bufs(inp, out)
+        st = stream if stream is not None else torch.cuda.current_stream(inp.device)
+        _check(_lib.jt_batch_run_static(self._h, i, o, _vp(st.cuda_stream)))
         return out
 
     def capture(self, inp, out):

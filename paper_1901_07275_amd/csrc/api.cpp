@@ -134,7 +134,7 @@ jt_plan_s *build_plan(int d, const int *n, const double *a, const double *b, dou
 
 extern "C" {
 
-int jt_version(void) { return 120; }
+int jt_version(void) { return 121; }
 
 const char *jt_last_error(void) { return g_err.c_str(); }
 

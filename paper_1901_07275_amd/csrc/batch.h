@@ -104,4 +104,14 @@ constexpr int kDenseMaxLine = kDenseMax;
 // Zero the counters and launch the persistent kernel on `stream`.
 hipError_t launch_batch(const BatchLaunch &b, hipStream_t stream);
 
+// Counters of runs that bring no counter memory of their own: a
+// library-owned array of this many 32-bit words per device (256 KiB), kept
+// until the process ends.  Every such run on one device shares it.
+constexpr int kStaticCounterWords = 1 << 16;
+// Device address of that array on the current device (looked up once per
+// device, then cached).  Returns the lookup's error, if any.
+hipError_t static_counters(uint32_t **ptr);
+// Copy one 32-bit word on the device (a one-thread kernel on `stream`).
+hipError_t copy_word(uint32_t *dst, const uint32_t *src, hipStream_t stream);
+
 }  // namespace jt

@@ -10,11 +10,19 @@
 // a unit holds (groups / S) * LPB lines.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "batch.h"
 #include "dense_pass.h"
 #include "fft_line.h"
 
 namespace jt {
+
+// The counters of runs that bring none of their own (jt_batch_run_static).
+// In host code this name is only a handle for the symbol lookup below; the
+// array's device address comes from hipGetSymbolAddress, per device.
+static __device__ __align__(256) uint32_t scratch[kStaticCounterWords];
+
 namespace {
 
 using namespace dev;
@@ -220,7 +228,39 @@ hipError_t launch_t(const BatchLaunch &b, hipStream_t s)
     return hipGetLastError();
 }
 
+__global__ void __launch_bounds__(64) copy_word_kernel(uint32_t *dst, const uint32_t *src)
+{
+    if (threadIdx.x == 0) *dst = *src;
+}
+
 }  // namespace
+
+hipError_t static_counters(uint32_t **ptr)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static uint32_t *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = static_cast<uint32_t *>(p);
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
+}
+
+hipError_t copy_word(uint32_t *dst, const uint32_t *src, hipStream_t stream)
+{
+    hipLaunchKernelGGL(copy_word_kernel, dim3(1), dim3(64), 0, stream, dst, src);
+    return hipGetLastError();
+}
 
 hipError_t launch_batch(const BatchLaunch &b, hipStream_t stream)
 {

@@ -230,6 +230,32 @@ jt_status jt_batch_run(jt_batch_t batch, const void *in_base, void *out_base, vo
     return ok();
 }
 
+jt_status jt_batch_run_static(jt_batch_t batch, const void *in_base, void *out_base, void *stream)
+{
+    if (!batch || !in_base || !out_base) return fail(JT_EINVAL, "null argument");
+    const long long words = 2LL + (long long)batch->q.passes.size();
+    if (words > jt::kStaticCounterWords)
+        return fail(JT_EINVAL, "batch has " + std::to_string(batch->q.passes.size()) +
+                                   " axis passes; the library's counter array holds at most " +
+                                   std::to_string(jt::kStaticCounterWords - 2));
+    if (!batch->dev) return fail(JT_ESTATE, "batch is not bound (jt_batch_bind)");
+    if (in_base == out_base && batch->tin != batch->tout) return fail(JT_EINVAL, "in-place batch needs equal dtypes");
+    if (batch->q.units.empty()) return ok();
+    uint32_t *ctr = nullptr;
+    hipError_t e = jt::static_counters(&ctr);
+    if (e != hipSuccess)
+        return fail(JT_EDEVICE, std::string("cannot find the device counter array: ") + hipGetErrorString(e));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    jt::BatchLaunch b = launch_args(batch, in_base, out_base);
+    b.counters = ctr;
+    e = jt::launch_batch(b, s);
+    // the run's error word goes to the batch's own slot, where jt_batch_errors reads it
+    if (e == hipSuccess)
+        e = jt::copy_word(reinterpret_cast<uint32_t *>(batch->dev + batch->q.off_counters) + 1, ctr + 1, s);
+    if (e != hipSuccess) return fail(JT_EDEVICE, std::string("batch launch failed: ") + hipGetErrorString(e));
+    return ok();
+}
+
 jt_status jt_batch_capture(jt_batch_t batch, const void *in_base, void *out_base)
 {
     if (!batch || !in_base || !out_base) return fail(JT_EINVAL, "null argument");
