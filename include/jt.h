@@ -108,6 +108,28 @@ jt_status jt_plan(int d, const int *n, const double *a, const double *b, double 
 jt_status jt_plan_ex(int d, const int *n, const double *a, const double *b, double tol,
                      const jt_plan_options *opt, jt_plan_t *out);
 
+/*
+ * Plan the nonuniform forward transform at given points (Section 3.1, the
+ * remark on nonuniform transforms after eq. (39) and after eq. (51); Sections
+ * 3.2-3.3 for 2D and 3D): along axis i, f_j = sum_k alpha_k Ptilde_k(t_{i,j})
+ * with the modified Jacobi functions Ptilde_k(t) = sqrt(w(cos t) sin t)
+ * phat_k(cos t) (Section 1) and no quadrature weights, computed like the
+ * uniform transform (direct block of low degrees plus r scaled FFTs, eq.
+ * (50)) with the DFT bins [t_j L / 2 pi] of the given points.
+ *   d, n, a, b, tol, opt : as jt_plan_ex; axis i has n[i] points and n[i]
+ *                          coefficients (the square transform of the paper)
+ *   t    : the points of every axis concatenated (sum of n[i] values, host
+ *          fp64), each axis' points non-decreasing and inside (0, pi)
+ * Only jt_forward (and jt_apply_axis / batch items in the forward direction)
+ * accept such a plan: its inverse is an ill-conditioned solve, not the
+ * transpose, and the transpose calls return JT_EUNSUPPORTED.  jt_plan_nodes
+ * returns the points, their cosines and omega = 0.
+ * Errors: JT_EINVAL (bad argument, points outside (0, pi) or decreasing),
+ * JT_ENOMEM, JT_ENOTCONV.
+ */
+jt_status jt_plan_points(int d, const int *n, const double *t, const double *a, const double *b, double tol,
+                         const jt_plan_options *opt, jt_plan_t *out);
+
 /* Release a plan (host memory only; the caller still owns the bound device buffer).
  * NULL is accepted. */
 jt_status jt_plan_destroy(jt_plan_t plan);

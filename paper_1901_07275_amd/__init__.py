@@ -102,6 +102,8 @@ SYMBOLS = {
     "jt_plan": [ctypes.c_int, _ip, _dp, _dp, ctypes.c_double, ctypes.POINTER(_vp)],
     "jt_plan_ex": [ctypes.c_int, _ip, _dp, _dp, ctypes.c_double, ctypes.POINTER(PlanOptions),
                    ctypes.POINTER(_vp)],
+    "jt_plan_points": [ctypes.c_int, _ip, _dp, _dp, _dp, ctypes.c_double, ctypes.POINTER(PlanOptions),
+                       ctypes.POINTER(_vp)],
     "jt_plan_destroy": [_vp],
     "jt_plan_dims": [_vp, _ip],
     "jt_plan_info": [_vp, ctypes.c_int, ctypes.POINTER(AxisInfo)],
@@ -195,6 +197,33 @@ class Plan:
         _check(_lib.jt_plan_ex(d, nn, aa, bb, self.tol, ctypes.byref(opt), ctypes.byref(h)))
         self._h = h
         self._dev = None
+
+    @classmethod
+    def at_points(cls, points, ab: Sequence[Sequence[float]], tol: float, nu0: int = 0, dense_below: int = -1,
+                  oversample: int = 0, iterations: int = 0, seed: int = 0):
+        """Plan of the nonuniform forward transform (jt_plan_points): points[i]
+        holds axis i's angles in (0, pi), non-decreasing; that axis has as many
+        coefficients as points.  Only forward() applies it."""
+        pts = [np.ascontiguousarray(p, dtype=np.float64).ravel() for p in points]
+        self = cls.__new__(cls)
+        self.n = tuple(len(p) for p in pts)
+        self.ab = tuple((float(a), float(b)) for a, b in ab)
+        if len(self.ab) != len(self.n):
+            raise ValueError("need one (a, b) pair per axis")
+        self.tol = float(tol)
+        d = len(self.n)
+        flat = np.concatenate(pts) if pts else np.zeros(0)
+        nn = (ctypes.c_int * d)(*self.n)
+        aa = (ctypes.c_double * d)(*[p[0] for p in self.ab])
+        bb = (ctypes.c_double * d)(*[p[1] for p in self.ab])
+        opt = PlanOptions(nu0, dense_below, oversample, iterations, seed)
+        h = _vp()
+        self._h = None
+        self._dev = None
+        _check(_lib.jt_plan_points(d, nn, _dptr(flat), aa, bb, self.tol, ctypes.byref(opt), ctypes.byref(h)))
+        self._h = h
+        self.points = pts
+        return self
 
     @classmethod
     def _adopt(cls, handle, n, ab, tol):

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <exception>
 #include <new>
@@ -47,6 +48,9 @@ jt_status run_axis(jt_plan_t p, int axis, bool forward, const void *in, jt_dtype
     if (prec != JT_PREC_FP64 && prec != JT_PREC_FP32_BULK) return fail(JT_EINVAL, "bad precision");
     if (in == out && tin != tout) return fail(JT_EINVAL, "in-place pass needs equal input and output dtypes");
     const jt::AxisPlan &ax = p->ax[axis];
+    if (ax.points && !forward)
+        return fail(JT_EUNSUPPORTED, "a plan at given points has only the forward transform (its inverse "
+                                     "is an ill-conditioned solve, not a transpose)");
     long long stride = 1;
     for (int i = axis + 1; i < p->d; ++i) stride *= p->ax[i].n;
     jt::AxisLaunch a;
@@ -109,15 +113,22 @@ PlanOptions plan_options(const jt_plan_options *opt)
     return po;
 }
 
-jt_plan_s *build_plan(int d, const int *n, const double *a, const double *b, double tol, const PlanOptions &po)
+jt_plan_s *build_plan(int d, const int *n, const double *a, const double *b, double tol, const PlanOptions &po,
+                      const double *t)
 {
     if (d < 1 || d > 3) throw std::invalid_argument("d must be 1, 2 or 3");
     jt_plan_s *p = new jt_plan_s();
     try {
         p->d = d;
         size_t off = 0;
+        size_t t0 = 0;
         for (int i = 0; i < d; ++i) {
-            build_axis(p->ax[i], n[i], a[i], b[i], tol, po);
+            if (t) {
+                build_axis_points(p->ax[i], n[i], t + t0, a[i], b[i], tol, po);
+                t0 += (size_t)std::max(n[i], 0);
+            } else {
+                build_axis(p->ax[i], n[i], a[i], b[i], tol, po);
+            }
             off = layout_axis(p->ax[i], off);
         }
         p->dev_bytes = off;
@@ -134,7 +145,7 @@ jt_plan_s *build_plan(int d, const int *n, const double *a, const double *b, dou
 
 extern "C" {
 
-int jt_version(void) { return 121; }
+int jt_version(void) { return 122; }
 
 const char *jt_last_error(void) { return g_err.c_str(); }
 
@@ -147,6 +158,19 @@ jt_status jt_plan_ex(int d, const int *n, const double *a, const double *b, doub
         if (d < 1 || d > 3) return fail(JT_EINVAL, "d must be 1, 2 or 3");
         if (!n || !a || !b) return fail(JT_EINVAL, "null parameter array");
         *out = jt::build_plan(d, n, a, b, tol, jt::plan_options(opt));
+        return ok();
+    });
+}
+
+jt_status jt_plan_points(int d, const int *n, const double *t, const double *a, const double *b, double tol,
+                         const jt_plan_options *opt, jt_plan_t *out)
+{
+    return guarded([&]() -> jt_status {
+        if (!out) return fail(JT_EINVAL, "null output handle");
+        *out = nullptr;
+        if (d < 1 || d > 3) return fail(JT_EINVAL, "d must be 1, 2 or 3");
+        if (!n || !a || !b || !t) return fail(JT_EINVAL, "null parameter array");
+        *out = jt::build_plan(d, n, a, b, tol, jt::plan_options(opt), t);
         return ok();
     });
 }

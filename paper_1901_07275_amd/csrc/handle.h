@@ -58,7 +58,9 @@ jt_status guarded(F f)
 }
 
 // Build one plan (host).  Throws on failure.
-jt_plan_s *build_plan(int d, const int *n, const double *a, const double *b, double tol, const PlanOptions &po);
+// With t (the axes' points concatenated): the nonuniform forward transform.
+jt_plan_s *build_plan(int d, const int *n, const double *a, const double *b, double tol, const PlanOptions &po,
+                      const double *t = nullptr);
 // Plan options from the ABI struct (NULL: defaults).
 PlanOptions plan_options(const jt_plan_options *opt);
 

@@ -661,13 +661,18 @@ static void rsvd(const Evaluator &E, double tol, const PlanOptions &opt, uint64_
 }
 
 // ------------------------------------------------------------------ build
-void build_axis(AxisPlan &ax, int n, double a, double b, double tol, const PlanOptions &opt)
+static void check_axis_args(int n, double a, double b, double tol, const PlanOptions &opt)
 {
     if (n < 1 || n > (1 << 14)) throw std::invalid_argument("n must be in [1, 16384]");
     if (!(a > -1.0) || !(b > -1.0) || !(a < 1.0) || !(b < 1.0))
         throw std::invalid_argument("a and b must lie in (-1, 1)");
     if (!(tol >= 1e-14) || !(tol <= 1e-2)) throw std::invalid_argument("tol must lie in [1e-14, 1e-2]");
     if (opt.nu0 < 1 || opt.nu0 > kMaxNu0) throw std::invalid_argument("nu0 must lie in [1, 64]");
+}
+
+// Sizes, direct-block width and seed of an axis; the evaluator's shape.
+static void start_axis(AxisPlan &ax, Evaluator &E, int n, double a, double b, double tol, const PlanOptions &opt)
+{
     ax = AxisPlan();
     ax.n = n; ax.a = a; ax.b = b; ax.tol = tol;
     int L = 64;
@@ -677,32 +682,37 @@ void build_axis(AxisPlan &ax, int n, double a, double b, double tol, const PlanO
     // longest line the matrix-core pass takes
     ax.nu0 = (n < opt.dense_below && n <= 1024) ? n : std::min(opt.nu0, n);
     ax.seed = opt.seed ? opt.seed : mix_key(n, a, b, tol);
-
-    Rec rec = recurrence(n + 1, a, b);
-    std::vector<ld> tl, wl;
-    nodes_ld(rec, n, a, b, tl, wl);
-    Evaluator E;
-    E.n = n; E.nu0 = ax.nu0; E.L = L; E.Nc = n - ax.nu0; E.rec = rec;
+    E.n = n; E.nu0 = ax.nu0; E.L = L; E.Nc = n - ax.nu0;
+    E.rec = recurrence(n + 1, a, b);
     E.x.resize(n); E.sw.resize(n); E.invpw.resize(n); E.q0.resize(n); E.m.resize(n);
     ax.t.resize(n); ax.x.resize(n); ax.omega.resize(n); ax.bins.resize(n);
-    parallel_for(n, [&](int j) {
-        ld t = tl[j];
-        ld xj = cosl(t);
-        ld om = wl[j];
-        ld sh = sinl(t / 2), ch = cosl(t / 2);
-        ld omx = 2 * sh * sh, opx = 2 * ch * ch;  // 1 - x, 1 + x without cancellation
-        ld wx = powl(omx, (ld)a) * powl(opx, (ld)b);
-        E.x[j] = xj;
-        E.sw[j] = sqrtl(om);
-        E.invpw[j] = 1 / (kPi * wx);
-        E.m[j] = (int)llrintl(t * L / (2 * kPi));
-        ax.t[j] = (double)t;
-        ax.x[j] = (double)xj;
-        ax.omega[j] = (double)om;
-        ax.bins[j] = E.m[j];
-        if (E.Nc > 0) E.q0[j] = hilbert_weight_parts(omx, opx, a, b) / rec.sqrt_mu0;
-    });
-    // bins are non-decreasing (nodes ascend in t); CSR over m = 0 .. L/2
+}
+
+// Per-point values at angle t with row scale sw: the point, its bin
+// m = [t L / 2 pi] (eq. (45)), 1 / (pi w(x)) and q_0(x) for the companion.
+static void set_point(AxisPlan &ax, Evaluator &E, int j, ld t, ld sw, ld om)
+{
+    const ld xj = cosl(t);
+    const ld sh = sinl(t / 2), ch = cosl(t / 2);
+    const ld omx = 2 * sh * sh, opx = 2 * ch * ch;  // 1 - x, 1 + x without cancellation
+    const ld wx = powl(omx, (ld)ax.a) * powl(opx, (ld)ax.b);
+    E.x[j] = xj;
+    E.sw[j] = sw;
+    E.invpw[j] = 1 / (kPi * wx);
+    E.m[j] = (int)llrintl(t * ax.L / (2 * kPi));
+    ax.t[j] = (double)t;
+    ax.x[j] = (double)xj;
+    ax.omega[j] = (double)om;
+    ax.bins[j] = E.m[j];
+    if (E.Nc > 0) E.q0[j] = hilbert_weight_parts(omx, opx, ax.a, ax.b) / E.rec.sqrt_mu0;
+}
+
+// Everything after the points: bin table, direct block, DFT phases and the
+// randomized factorization of the low-rank part.
+static void finish_axis(AxisPlan &ax, Evaluator &E, const PlanOptions &opt)
+{
+    const int n = ax.n, L = ax.L;
+    // bins are non-decreasing (points ascend in t); CSR over m = 0 .. L/2
     const int nb = L / 2 + 1;
     ax.binptr.assign(nb + 1, 0);
     for (int j = 0; j < n; ++j) {
@@ -726,9 +736,44 @@ void build_axis(AxisPlan &ax, int n, double a, double b, double tol, const PlanO
         ld ang = -2 * kPi * p / L;
         E.ph[p] = cd((double)cosl(ang), (double)sinl(ang));
     }
-    E.dbl_cols = tol >= 1e-10;
+    E.dbl_cols = ax.tol >= 1e-10;
     if (E.Nc > 0)
-        rsvd(E, tol, opt, ax.seed, ax);
+        rsvd(E, ax.tol, opt, ax.seed, ax);
+}
+
+void build_axis(AxisPlan &ax, int n, double a, double b, double tol, const PlanOptions &opt)
+{
+    check_axis_args(n, a, b, tol, opt);
+    Evaluator E;
+    start_axis(ax, E, n, a, b, tol, opt);
+    std::vector<ld> tl, wl;
+    nodes_ld(E.rec, n, a, b, tl, wl);
+    // uniform transform: rows weighted by sqrt(omega_j) (Section 3.1, eq. (37))
+    parallel_for(n, [&](int j) { set_point(ax, E, j, tl[j], sqrtl(wl[j]), wl[j]); });
+    finish_axis(ax, E, opt);
+}
+
+void build_axis_points(AxisPlan &ax, int n, const double *t, double a, double b, double tol,
+                       const PlanOptions &opt)
+{
+    check_axis_args(n, a, b, tol, opt);
+    if (!t) throw std::invalid_argument("null point array");
+    for (int j = 0; j < n; ++j) {
+        if (!(t[j] > 0.0) || !(t[j] < 3.14159265358979323846)) throw std::invalid_argument("points must lie in (0, pi)");
+        if (j && !(t[j] >= t[j - 1])) throw std::invalid_argument("points must be non-decreasing");
+    }
+    Evaluator E;
+    start_axis(ax, E, n, a, b, tol, opt);
+    ax.points = true;
+    // nonuniform transform: the rows are Ptilde_k(t_j) themselves, no
+    // quadrature weights (Section 3.1): Ptilde_k(t) = sqrt(w(x) sin t) phat_k(x)
+    parallel_for(n, [&](int j) {
+        const ld tj = t[j];
+        const ld sh = sinl(tj / 2), ch = cosl(tj / 2);
+        const ld wsin = powl(2 * sh * sh, (ld)a) * powl(2 * ch * ch, (ld)b) * sinl(tj);
+        set_point(ax, E, j, tj, sqrtl(wsin), 0);
+    });
+    finish_axis(ax, E, opt);
 }
 
 void exact_entries(const AxisPlan &ax, int count, const int *rows, const int *degs, cd *out)
@@ -751,7 +796,7 @@ void exact_entries(const AxisPlan &ax, int count, const int *rows, const int *de
             pm = p; p = pn;
             qm = q; q = qn;
         }
-        ld sw = sqrtl((ld)ax.omega[j]);
+        ld sw = ax.points ? sqrtl(wx * sinl(t)) : sqrtl((ld)ax.omega[j]);
         int64_t e = ((int64_t)ax.bins[j] * k) % ax.L;
         ld ang = -2 * kPi * e / ax.L;
         cd z((double)(sw * p), (double)(sw * q / (kPi * wx)));

@@ -27,9 +27,10 @@ struct AxisPlan {
     int nu0 = 0;     // width of the direct block (27, or n for the dense path)
     int rank = 0;    // r
     int max_per_bin = 0;
+    bool points = false;  // nonuniform: given points, no quadrature weights (forward only)
     double a = 0.0, b = 0.0, tol = 0.0;
     uint64_t seed = 0;
-    std::vector<double> t, x, omega;  // nodes ascending in t, Gauss-Jacobi weights
+    std::vector<double> t, x, omega;  // nodes ascending in t, Gauss-Jacobi weights (0 for given points)
     std::vector<int32_t> bins;        // m_j in [0, L/2]
     std::vector<int32_t> binptr;      // nodes of bin m: [binptr[m], binptr[m+1]), m <= L/2
     std::vector<double> WV;           // nu0 x n, WV[k*n + j] = sqrt(omega_j) phat_k(x_j)
@@ -58,6 +59,11 @@ struct PlanOptions {
 
 // Build one axis.  Throws std::runtime_error on bad input or non-convergence.
 void build_axis(AxisPlan &ax, int n, double a, double b, double tol, const PlanOptions &opt);
+
+// Build one axis of the nonuniform forward transform at the given points
+// t[0..n-1] (non-decreasing, in (0, pi)): rows Ptilde_k(t_j), no weights.
+void build_axis_points(AxisPlan &ax, int n, const double *t, double a, double b, double tol,
+                       const PlanOptions &opt);
 
 // Exact entries of W B (the low-rank matrix with weights folded in) at
 // (row j, degree k) pairs, k in [nu0, n).  For diagnostics and tests.
