@@ -30,6 +30,15 @@ too slow for, and the nonuniform transform:
   nonuniform forward transform f = (P0 (x) P1 (x) ...) alpha with
   P_i[j, k] = Ptilde_k(t_{i,j}) (Section 3.1, the nonuniform remark after
   eq. (39); Sections 3.2-3.3 for 2D/3D), no quadrature weights.
+* ``qtilde`` / ``matrix_q`` / ``forward_q`` / ``forward_points_q``: the
+  modified Jacobi functions of the second kind (Section 1),
+  Qtilde_k(t) = sqrt(sin t / w(x)) q_k(x) / pi with q_k the finite Hilbert
+  transform of w phat_k (q_0 from Tricomi's closed form, then the
+  inhomogeneous three-term recurrence), and the second-kind transforms: the
+  uniform one with matrix sqrt(w_j) Qtilde_k(t_j) at the Gauss-Jacobi nodes
+  and the nonuniform one at given angles (Section 3: "the transform for
+  Qtilde is similar").  Parameters with exactly one of a, b equal to 0 are
+  not supported by the closed form (ValueError).
 """
 from __future__ import annotations
 
@@ -73,6 +82,10 @@ def _load():
         lib.orc_nodes_fp64.restype = ctypes.c_int
         lib.orc_apply_fp64.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, dp]
         lib.orc_apply_fp64.restype = ctypes.c_int
+        lib.orc_qtilde.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, dp]
+        lib.orc_qtilde.restype = ctypes.c_int
+        lib.orc_build_q.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp]
+        lib.orc_build_q.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -110,6 +123,7 @@ def recurrence(n: int, a: float, b: float):
 
 def clear_cache() -> None:
     _cache.clear()
+    _qcache.clear()
 
 
 def _apply(x: np.ndarray, params, transpose: bool) -> np.ndarray:
@@ -203,4 +217,54 @@ def forward_points(alpha: np.ndarray, params, points) -> np.ndarray:
     for axis, ((a, b), t) in enumerate(zip(params, points)):
         P = ptilde(x.shape[axis], a, b, t)
         x = np.moveaxis(np.tensordot(P, x, axes=([1], [axis])), 0, axis)
+    return np.ascontiguousarray(x)
+
+
+# ------------------------------------------------------------------ second kind
+def qtilde(n: int, a: float, b: float, t) -> np.ndarray:
+    """Q[j, k] = Qtilde_k(t_j) for k < n at the given angles t_j in (0, pi)."""
+    t = np.ascontiguousarray(t, dtype=np.float64).ravel()
+    out = np.empty((len(t), n))
+    rc = _load().orc_qtilde(int(n), float(a), float(b), len(t), _ptr(t), _ptr(out))
+    if rc != 0:
+        raise ValueError("oracle: qtilde unsupported or bad arguments (code %d) for a=%r b=%r" % (rc, a, b))
+    return out
+
+
+_qcache = {}
+
+
+def matrix_q(n: int, a: float, b: float) -> np.ndarray:
+    """The uniform second-kind matrix Q[j, k] = sqrt(w_j) Qtilde_k(t_j) at the
+    Gauss-Jacobi nodes (ascending t), w_j the trigonometric weights."""
+    key = (int(n), float(a), float(b))
+    if key not in _qcache:
+        Q = np.empty((n, n))
+        rc = _load().orc_build_q(int(n), float(a), float(b), _ptr(Q))
+        if rc != 0:
+            raise ValueError("oracle: second-kind matrix unsupported or bad arguments (code %d)" % rc)
+        _qcache[key] = Q
+    return _qcache[key]
+
+
+def forward_q(alpha: np.ndarray, params) -> np.ndarray:
+    """Uniform second-kind forward transform: Q_i along each axis i."""
+    x = np.asarray(alpha, dtype=np.float64)
+    if x.ndim != len(params):
+        raise ValueError("need one (a, b) pair per axis")
+    for axis, (a, b) in enumerate(params):
+        Q = matrix_q(x.shape[axis], a, b)
+        x = np.moveaxis(np.tensordot(Q, x, axes=([1], [axis])), 0, axis)
+    return np.ascontiguousarray(x)
+
+
+def forward_points_q(alpha: np.ndarray, params, points) -> np.ndarray:
+    """Nonuniform second-kind forward transform: along axis i apply
+    Q_i[j, k] = Qtilde_k(t_{i,j}); no quadrature weights."""
+    x = np.asarray(alpha, dtype=np.float64)
+    if x.ndim != len(params) or len(points) != x.ndim:
+        raise ValueError("need one (a, b) pair and one point set per axis")
+    for axis, ((a, b), t) in enumerate(zip(params, points)):
+        Q = qtilde(x.shape[axis], a, b, t)
+        x = np.moveaxis(np.tensordot(Q, x, axes=([1], [axis])), 0, axis)
     return np.ascontiguousarray(x)

@@ -507,3 +507,175 @@ int orc_apply_fp64(int n, double a, double b, int transpose, const double *v, do
     free(x); free(w);
     return rc;
 }
+
+/* ======================================================================
+ * Modified Jacobi functions of the second kind (Section 1: Qtilde_k, the
+ * companion of Ptilde_k in Ptilde_k + i Qtilde_k = M exp(i psi)).
+ *
+ * The paper defines Qtilde_k through the Jacobi function of the second kind
+ * and leaves its normalisation to the literature.  The reading used here
+ * (the one under which Ptilde_k + i Qtilde_k has a non-oscillatory amplitude
+ * and an increasing phase, and which reduces to the sine/cosine pairs of the
+ * Chebyshev cases) is
+ *
+ *     Qtilde_k(t) = sqrt(sin t / w(x)) q_k(x) / pi,   x = cos t,
+ *     q_k(x)      = PV int_{-1}^{1} w(s) phat_k(s) / (s - x) ds,
+ *
+ * i.e. the finite Hilbert transform of w phat_k.  From
+ * s phat_k = beta_{k+1} phat_{k+1} + alpha_k phat_k + beta_k phat_{k-1}:
+ *     beta_{k+1} q_{k+1} = (x - alpha_k) q_k - beta_k q_{k-1} + [k = 0] sqrt(mu0),
+ * and q_0 = H(x) / sqrt(mu0) with H(x) = PV int w(s) / (s - x) ds, written in
+ * closed form (Tricomi) for x >= 0:
+ *     H(x) = pi cot(pi a) w(x) - 2^(a+b) B(a, b+1) 2F1(1, -a-b; 1-a; (1-x)/2),
+ * whose series converges geometrically there ((1-x)/2 <= 1/2); for x < 0 the
+ * reflection H^(a,b)(x) = -H^(b,a)(-x) (substitute s -> -s).  For a = b = 0,
+ * H(x) = log((1-x)/(1+x)).  The closed form needs a and b away from 0 (the
+ * cotangent and Beta function have poles there); those parameters, other
+ * than a = b = 0, are refused (code 5).
+ * ====================================================================== */
+static ld orc_hilbert_pos(ld a, ld b, ld x)
+{
+    /* x >= 0, a, b not 0 */
+    const ld pi = 3.141592653589793238462643383279502884L;
+    ld z = (1.0L - x) / 2.0L;
+    ld term = 1.0L, sum = 1.0L;
+    for (int m = 0; m < 400; ++m) {
+        term *= ((ld)m - a - b) / ((ld)m + 1.0L - a) * z;
+        sum += term;
+        if (fabsl(term) <= 1e-22L * fabsl(sum)) break;
+    }
+    ld omx = 1.0L - x, opx = 1.0L + x;
+    ld w = powl(omx, a) * powl(opx, b);
+    /* B(a, b+1) = Gamma(a) Gamma(b+1) / Gamma(a+b+1), with signs (Gamma(a) < 0 for a in (-1, 0)) */
+    ld beta_ab = tgammal(a) * tgammal(b + 1.0L) / tgammal(a + b + 1.0L);
+    ld cot = cosl(pi * a) / sinl(pi * a);
+    return pi * cot * w - powl(2.0L, a + b) * beta_ab * sum;
+}
+
+static int orc_hilbert(ld a, ld b, ld x, ld *h)
+{
+    if (a == 0.0L && b == 0.0L) {
+        *h = logl((1.0L - x) / (1.0L + x));
+        return 0;
+    }
+    if (a == 0.0L || b == 0.0L)
+        return 5;
+    *h = (x >= 0.0L) ? orc_hilbert_pos(a, b, x) : -orc_hilbert_pos(b, a, -x);
+    return 0;
+}
+
+/* out: m x n row-major, out[j*n + k] = Qtilde_k(t_j) at t_j in (0, pi). */
+int orc_qtilde(int n, double a_in, double b_in, int m, const double *t_in, double *out)
+{
+    if (n < 1 || m < 0 || !(a_in > -1.0) || !(b_in > -1.0) || !(a_in < 1.0) || !(b_in < 1.0))
+        return 1;
+    if ((a_in == 0.0) != (b_in == 0.0))
+        return 5;
+    for (int j = 0; j < m; ++j)
+        if (!(t_in[j] > 0.0) || !(t_in[j] < 3.14159265358979323846))
+            return 3;
+    ld a = a_in, b = b_in;
+    ld *alpha = (ld *)malloc(sizeof(ld) * (n + 1));
+    ld *beta = (ld *)malloc(sizeof(ld) * (n + 1));
+    if (!alpha || !beta) {
+        free(alpha); free(beta);
+        return 2;
+    }
+    ld mu0;
+    orc_coeffs(n, a, b, alpha, beta, &mu0);
+    const ld pi = 3.141592653589793238462643383279502884L;
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (int j = 0; j < m; ++j) {
+        ld t = t_in[j];
+        ld sh = sinl(t / 2.0L), ch = cosl(t / 2.0L);
+        ld omx = 2.0L * sh * sh, opx = 2.0L * ch * ch; /* 1 - x, 1 + x */
+        ld x = cosl(t);
+        ld w = powl(omx, a) * powl(opx, b);
+        ld h;
+        if (orc_hilbert(a, b, x, &h)) { bad = 1; continue; }
+        ld scale = sqrtl(sinl(t) / w) / pi;
+        ld qm1 = 0.0L, qk = h / sqrtl(mu0);
+        for (int k = 0; k < n; ++k) {
+            out[(size_t)j * n + k] = (double)(scale * qk);
+            ld qn = ((x - alpha[k]) * qk - beta[k] * qm1 + (k == 0 ? sqrtl(mu0) : 0.0L)) / beta[k + 1];
+            qm1 = qk;
+            qk = qn;
+        }
+    }
+    free(alpha); free(beta);
+    return bad ? 5 : 0;
+}
+
+/* Uniform second-kind matrix at the Gauss-Jacobi nodes, the weighted
+ * counterpart of orc_build: Q[j][k] = sqrt(w_j) Qtilde_k(t_j) with the
+ * trigonometric weights w_j = omega_j / (w(x_j) sin t_j) of eq. (9), i.e.
+ * sqrt(omega_j) q_k(x_j) / (pi w(x_j)).  The nodes and weights are those of
+ * orc_build (same steps O1-O5), recomputed here in long double. */
+int orc_build_q(int n, double a_in, double b_in, double *Q)
+{
+    if (n < 1 || !(a_in > -1.0) || !(b_in > -1.0) || !(a_in < 1.0) || !(b_in < 1.0))
+        return 1;
+    if ((a_in == 0.0) != (b_in == 0.0))
+        return 5;
+    ld a = a_in, b = b_in;
+    ld *alpha = (ld *)malloc(sizeof(ld) * (n + 1));
+    ld *beta = (ld *)malloc(sizeof(ld) * (n + 1));
+    ld *x = (ld *)malloc(sizeof(ld) * n);
+    if (!alpha || !beta || !x) {
+        free(alpha); free(beta); free(x);
+        return 2;
+    }
+    ld mu0;
+    orc_coeffs(n, a, b, alpha, beta, &mu0);
+    /* nodes: bisection on the Sturm count, then Newton (as in orc_build) */
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int i = 0; i < n; ++i) {
+        ld lo = -1.0L, hi = 1.0L;
+        for (int it = 0; it < 80; ++it) {
+            ld mid = 0.5L * (lo + hi);
+            if (orc_sturm_count(n, alpha, beta, mid) > i)
+                hi = mid;
+            else
+                lo = mid;
+            if (hi - lo < 1e-13L)
+                break;
+        }
+        ld xi = 0.5L * (lo + hi);
+        for (int it = 0; it < 3; ++it) {
+            ld p, dp;
+            orc_eval_pn(n, alpha, beta, mu0, xi, &p, &dp);
+            if (dp != 0.0L)
+                xi -= p / dp;
+        }
+        x[n - 1 - i] = xi;
+    }
+    const ld pi = 3.141592653589793238462643383279502884L;
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (int j = 0; j < n; ++j) {
+        ld xj = x[j];
+        /* Christoffel weight */
+        ld pm1 = 0.0L, pk = 1.0L / sqrtl(mu0), sum = 0.0L;
+        for (int k = 0; k < n; ++k) {
+            sum += pk * pk;
+            ld pn = ((xj - alpha[k]) * pk - beta[k] * pm1) / beta[k + 1];
+            pm1 = pk;
+            pk = pn;
+        }
+        ld om = 1.0L / sum;
+        ld w = powl(1.0L - xj, a) * powl(1.0L + xj, b);
+        ld h;
+        if (orc_hilbert(a, b, xj, &h)) { bad = 1; continue; }
+        ld scale = sqrtl(om) / (pi * w);
+        ld qm1 = 0.0L, qk = h / sqrtl(mu0);
+        for (int k = 0; k < n; ++k) {
+            Q[(size_t)j * n + k] = (double)(scale * qk);
+            ld qn = ((xj - alpha[k]) * qk - beta[k] * qm1 + (k == 0 ? sqrtl(mu0) : 0.0L)) / beta[k + 1];
+            qm1 = qk;
+            qk = qn;
+        }
+    }
+    free(alpha); free(beta); free(x);
+    return bad ? 5 : 0;
+}

@@ -328,3 +328,125 @@ def test_fp64_path_orthogonal_at_the_largest_size(orc):
     g = orc.apply1d_fp64(v, ab)
     assert abs(np.linalg.norm(g) / np.linalg.norm(v) - 1) <= 1e-10
     assert np.linalg.norm(orc.apply1d_fp64(g, ab, True) - v) <= 1e-9 * np.linalg.norm(v)
+
+
+# ------------------------------------------------- second kind (Qtilde)
+# Chebyshev cases: with Ptilde_k + i Qtilde_k = M exp(i psi) and psi
+# increasing, the four Chebyshev kinds give Qtilde as the matching sine or
+# cosine (the finite Hilbert transforms of T_k, U_k, V_k and W_k with their
+# weights are multiples of U_{k-1}, T_{k+1}, W_k and V_k).
+_QTILDE_CLOSED = {
+    (-0.5, -0.5): lambda k, t: np.where(k == 0, 0.0, np.sqrt(2 / np.pi) * np.sin(k * t)),
+    (0.5, 0.5): lambda k, t: -np.sqrt(2 / np.pi) * np.cos((k + 1) * t),
+    (-0.5, 0.5): lambda k, t: np.sqrt(2 / np.pi) * np.sin((k + 0.5) * t),
+    (0.5, -0.5): lambda k, t: -np.sqrt(2 / np.pi) * np.cos((k + 0.5) * t),
+}
+
+
+@pytest.mark.parametrize("ab", list(_QTILDE_CLOSED))
+def test_qtilde_chebyshev_closed_forms(orc, ab):
+    n = 300
+    t = np.sort(np.random.default_rng(22).uniform(1e-3, np.pi - 1e-3, 97))
+    Q = orc.qtilde(n, ab[0], ab[1], t)
+    ref = _QTILDE_CLOSED[ab](np.arange(n)[None, :], t[:, None])
+    assert np.abs(Q - ref).max() <= 1e-12
+
+
+def test_uniform_second_kind_matrix_chebyshev(orc):
+    """a = b = -1/2: nodes (2j-1) pi / 2n, trigonometric weights pi / n, so the
+    matrix is sqrt(2/n) sin(k t_j) (k >= 1) with a zero first column."""
+    n = 64
+    Q = orc.matrix_q(n, -0.5, -0.5)
+    t = (2 * np.arange(1, n + 1) - 1) * np.pi / (2 * n)
+    k = np.arange(n)[None, :]
+    ref = np.where(k == 0, 0.0, np.sqrt(2.0 / n) * np.sin(k * t[:, None]))
+    assert np.abs(Q - ref).max() <= 1e-13
+
+
+def _q_mpmath(k, a, b, x):
+    """q_k(x) = PV int w(s) phat_k(s) / (s - x) ds at 30 digits: the principal
+    value written as a regular integral plus w(x) phat_k(x) log((1-x)/(1+x)),
+    each half mapped so that the endpoint power singularity goes away
+    (s = 1 - (1-x) v^p with p = 1/(1+a) on the right, likewise on the left)."""
+    with mp.workdps(30):
+        a, b, x = mp.mpf(a), mp.mpf(b), mp.mpf(x)
+        hk = (2 ** (a + b + 1) / (2 * k + a + b + 1) * mp.gamma(k + a + 1) * mp.gamma(k + b + 1)
+              / (mp.gamma(k + a + b + 1) * mp.factorial(k)))
+        ph = lambda s: mp.jacobi(k, a, b, s) / mp.sqrt(hk)  # noqa: E731
+        wx = (1 - x) ** a * (1 + x) ** b
+        fx = wx * ph(x)
+        pa, pb = max(mp.mpf(1), 1 / (1 + a)), max(mp.mpf(1), 1 / (1 + b))
+
+        def right(v):
+            s = 1 - (1 - x) * v ** pa
+            ws = (1 - x) ** a * v ** (pa * (1 + a) - 1) * (1 + s) ** b * ph(s)
+            return (ws - fx * v ** (pa - 1)) / (s - x) * (1 - x) * pa
+
+        def left(v):
+            s = -1 + (1 + x) * v ** pb
+            ws = (1 + x) ** b * v ** (pb * (1 + b) - 1) * (1 - s) ** a * ph(s)
+            return (ws - fx * v ** (pb - 1)) / (s - x) * (1 + x) * pb
+
+        return mp.quad(left, [0, 1]) + mp.quad(right, [0, 1]) + fx * mp.log((1 - x) / (1 + x))
+
+
+@pytest.mark.parametrize("a,b", [(0.25, -0.35), (-0.8, 0.6), (0.9, 0.3), (-0.95, -0.9)])
+def test_qtilde_against_principal_value_quadrature(orc, a, b):
+    """Independent of the oracle's closed form for q_0 and of its recurrence:
+    every q_k (k < 8) from its own principal-value integral."""
+    xs = [-0.99, -0.7, 0.2, 0.95]
+    t = np.arccos(xs)
+    Q = orc.qtilde(8, a, b, t)
+    for j, x in enumerate(xs):
+        w = (1 - x) ** a * (1 + x) ** b
+        for k in range(8):
+            ref = float(mp.sqrt(mp.sin(t[j]) / w) * _q_mpmath(k, a, b, x) / mp.pi)
+            assert abs(Q[j, k] - ref) <= 1e-13 * max(1.0, abs(ref)), (x, k, Q[j, k], ref)
+
+
+def test_first_and_second_kind_share_a_non_oscillatory_amplitude(orc):
+    """Ptilde_k^2 + Qtilde_k^2 = M^2 varies slowly and tends to 2/pi at high
+    degree away from the endpoints (a dropped 1/pi or a wrong power of
+    w(x) / sin t in Qtilde breaks this)."""
+    t = np.linspace(0.4, np.pi - 0.4, 50)
+    for a, b in ((0.25, -0.35), (-0.4, 0.1), (0.45, 0.45)):
+        P, Q = orc.ptilde(401, a, b, t), orc.qtilde(401, a, b, t)
+        m2 = P[:, 400] ** 2 + Q[:, 400] ** 2
+        assert np.abs(m2 - 2 / np.pi).max() <= 2e-3
+        # smooth in t: no oscillation at the degree's frequency
+        assert np.abs(np.diff(m2, 2)).max() <= 1e-4
+
+
+def test_qtilde_swapped_parameters_fail_the_pin(orc):
+    t = np.linspace(0.1, 3.0, 11)
+    Q = orc.qtilde(20, 0.5, -0.5, t)
+    ref = _QTILDE_CLOSED[(-0.5, 0.5)](np.arange(20)[None, :], t[:, None])
+    assert np.abs(Q - ref).max() > 0.1
+
+
+def test_uniform_second_kind_is_the_weighted_nonuniform_one(orc):
+    n, a, b = 200, 0.3, -0.45
+    A, x, om = orc.matrix(n, a, b)
+    t = np.arccos(x)
+    w_trig = om / ((1 - x) ** a * (1 + x) ** b * np.sin(t))
+    assert np.abs(np.sqrt(w_trig)[:, None] * orc.qtilde(n, a, b, t) - orc.matrix_q(n, a, b)).max() <= 1e-11
+
+
+def test_second_kind_refuses_parameters_the_closed_form_lacks(orc):
+    with pytest.raises(ValueError):
+        orc.qtilde(10, 0.0, 0.3, [1.0])
+    assert np.all(np.isfinite(orc.qtilde(10, 0.0, 0.0, [0.5, 1.0])))
+
+
+def test_qtilde_legendre_against_scipy(orc):
+    """a = b = 0: q_k = PV int phat_k(s) / (s - x) ds = -2 sqrt(k + 1/2) Q_k(x)
+    with Q_k the Legendre function of the second kind (Neumann's integral),
+    from scipy.special.lqn."""
+    from scipy.special import lqn
+
+    xs = np.array([-0.9, -0.3, 0.1, 0.6, 0.97])
+    Q = orc.qtilde(30, 0.0, 0.0, np.arccos(xs))
+    for j, x in enumerate(xs):
+        ql, _ = lqn(29, x)
+        ref = np.sqrt(np.sin(np.arccos(x))) * (-2 * np.sqrt(np.arange(30) + 0.5) * ql) / np.pi
+        assert np.abs(Q[j] - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
