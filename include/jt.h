@@ -74,6 +74,13 @@ typedef struct {
     int oversample;   /* q of Algorithm 2.1; default 2 */
     int iterations;   /* repetitions of steps 2-3 of Algorithm 2.1; default 2 (Section 2.1) */
     uint64_t seed;    /* 0: derived from (n, a, b, tol), so plans are reproducible */
+    int kind;         /* 0 or 1: the transform of the modified Jacobi functions of the first
+                         kind Ptilde_k; 2: of the second kind Qtilde_k (Section 1; Section 3:
+                         "the transform for Qtilde is similar"), read as
+                         Qtilde_k(t) = sqrt(sin t / w(x)) q_k(x) / pi with q_k the finite
+                         Hilbert transform of w phat_k, i.e. the imaginary part of W B of
+                         eq. (45) before the DFT phase.  A second-kind plan has only the
+                         forward transform (its matrix is not orthogonal) */
 } jt_plan_options;
 
 /* Per-axis facts about a plan. */

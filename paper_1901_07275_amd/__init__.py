@@ -52,7 +52,7 @@ _STATUS = {0: "JT_OK", 1: "JT_EINVAL", 2: "JT_ENOMEM", 3: "JT_EDEVICE", 4: "JT_E
 
 class PlanOptions(ctypes.Structure):
     _fields_ = [("nu0", ctypes.c_int), ("dense_below", ctypes.c_int), ("oversample", ctypes.c_int),
-                ("iterations", ctypes.c_int), ("seed", ctypes.c_uint64)]
+                ("iterations", ctypes.c_int), ("seed", ctypes.c_uint64), ("kind", ctypes.c_int)]
 
 
 class AxisInfo(ctypes.Structure):
@@ -182,7 +182,7 @@ class Plan:
 
     def __init__(self, n: Sequence[int], ab: Sequence[Sequence[float]], tol: float,
                  nu0: int = 0, dense_below: int = -1, oversample: int = 0, iterations: int = 0,
-                 seed: int = 0):
+                 seed: int = 0, kind: int = 1):
         self.n = tuple(int(v) for v in n)
         self.ab = tuple((float(a), float(b)) for a, b in ab)
         if len(self.ab) != len(self.n):
@@ -192,7 +192,7 @@ class Plan:
         nn = (ctypes.c_int * d)(*self.n)
         aa = (ctypes.c_double * d)(*[p[0] for p in self.ab])
         bb = (ctypes.c_double * d)(*[p[1] for p in self.ab])
-        opt = PlanOptions(nu0, dense_below, oversample, iterations, seed)
+        opt = PlanOptions(nu0, dense_below, oversample, iterations, seed, kind)
         h = _vp()
         _check(_lib.jt_plan_ex(d, nn, aa, bb, self.tol, ctypes.byref(opt), ctypes.byref(h)))
         self._h = h
@@ -200,7 +200,7 @@ class Plan:
 
     @classmethod
     def at_points(cls, points, ab: Sequence[Sequence[float]], tol: float, nu0: int = 0, dense_below: int = -1,
-                  oversample: int = 0, iterations: int = 0, seed: int = 0):
+                  oversample: int = 0, iterations: int = 0, seed: int = 0, kind: int = 1):
         """Plan of the nonuniform forward transform (jt_plan_points): points[i]
         holds axis i's angles in (0, pi), non-decreasing; that axis has as many
         coefficients as points.  Only forward() applies it."""
@@ -216,7 +216,7 @@ class Plan:
         nn = (ctypes.c_int * d)(*self.n)
         aa = (ctypes.c_double * d)(*[p[0] for p in self.ab])
         bb = (ctypes.c_double * d)(*[p[1] for p in self.ab])
-        opt = PlanOptions(nu0, dense_below, oversample, iterations, seed)
+        opt = PlanOptions(nu0, dense_below, oversample, iterations, seed, kind)
         h = _vp()
         self._h = None
         self._dev = None

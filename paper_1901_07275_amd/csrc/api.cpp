@@ -48,9 +48,10 @@ jt_status run_axis(jt_plan_t p, int axis, bool forward, const void *in, jt_dtype
     if (prec != JT_PREC_FP64 && prec != JT_PREC_FP32_BULK) return fail(JT_EINVAL, "bad precision");
     if (in == out && tin != tout) return fail(JT_EINVAL, "in-place pass needs equal input and output dtypes");
     const jt::AxisPlan &ax = p->ax[axis];
-    if (ax.points && !forward)
-        return fail(JT_EUNSUPPORTED, "a plan at given points has only the forward transform (its inverse "
-                                     "is an ill-conditioned solve, not a transpose)");
+    if ((ax.points || ax.kind == 2) && !forward)
+        return fail(JT_EUNSUPPORTED, "a plan at given points or of the second kind has only the forward "
+                                     "transform (its matrix is not orthogonal: the inverse is a solve, "
+                                     "not the transpose)");
     long long stride = 1;
     for (int i = axis + 1; i < p->d; ++i) stride *= p->ax[i].n;
     jt::AxisLaunch a;
@@ -109,6 +110,7 @@ PlanOptions plan_options(const jt_plan_options *opt)
         if (opt->oversample > 0) po.oversample = opt->oversample;
         if (opt->iterations > 0) po.iterations = opt->iterations;
         po.seed = opt->seed;
+        if (opt->kind != 0) po.kind = opt->kind;
     }
     return po;
 }
@@ -145,7 +147,7 @@ jt_plan_s *build_plan(int d, const int *n, const double *a, const double *b, dou
 
 extern "C" {
 
-int jt_version(void) { return 122; }
+int jt_version(void) { return 123; }
 
 const char *jt_last_error(void) { return g_err.c_str(); }
 

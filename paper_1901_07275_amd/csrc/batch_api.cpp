@@ -117,9 +117,9 @@ jt_status jt_batch_create(int count, const jt_plan_t *plans, const int *dirs, co
             if (!p) return fail(JT_EINVAL, "item " + std::to_string(i) + ": null plan");
             if (dirs[i] != JT_FORWARD && dirs[i] != JT_INVERSE)
                 return fail(JT_EINVAL, "item " + std::to_string(i) + ": bad direction");
-            if (dirs[i] == JT_INVERSE && p->ax[0].points)
-                return fail(JT_EUNSUPPORTED, "item " + std::to_string(i) + ": a plan at given points has only "
-                                             "the forward transform");
+            if (dirs[i] == JT_INVERSE && (p->ax[0].points || p->ax[0].kind == 2))
+                return fail(JT_EUNSUPPORTED, "item " + std::to_string(i) + ": a plan at given points or of the "
+                                             "second kind has only the forward transform");
             jt::QueueItem it;
             it.d = p->d;
             for (int k = 0; k < p->d; ++k) it.ax[k] = &p->ax[k];

@@ -668,6 +668,7 @@ static void check_axis_args(int n, double a, double b, double tol, const PlanOpt
         throw std::invalid_argument("a and b must lie in (-1, 1)");
     if (!(tol >= 1e-14) || !(tol <= 1e-2)) throw std::invalid_argument("tol must lie in [1e-14, 1e-2]");
     if (opt.nu0 < 1 || opt.nu0 > kMaxNu0) throw std::invalid_argument("nu0 must lie in [1, 64]");
+    if (opt.kind != 1 && opt.kind != 2) throw std::invalid_argument("kind must be 1 (first) or 2 (second)");
 }
 
 // Sizes, direct-block width and seed of an axis; the evaluator's shape.
@@ -682,6 +683,7 @@ static void start_axis(AxisPlan &ax, Evaluator &E, int n, double a, double b, do
     // longest line the matrix-core pass takes
     ax.nu0 = (n < opt.dense_below && n <= 1024) ? n : std::min(opt.nu0, n);
     ax.seed = opt.seed ? opt.seed : mix_key(n, a, b, tol);
+    ax.kind = opt.kind;
     E.n = n; E.nu0 = ax.nu0; E.L = L; E.Nc = n - ax.nu0;
     E.rec = recurrence(n + 1, a, b);
     E.x.resize(n); E.sw.resize(n); E.invpw.resize(n); E.q0.resize(n); E.m.resize(n);
@@ -704,7 +706,7 @@ static void set_point(AxisPlan &ax, Evaluator &E, int j, ld t, ld sw, ld om)
     ax.x[j] = (double)xj;
     ax.omega[j] = (double)om;
     ax.bins[j] = E.m[j];
-    if (E.Nc > 0) E.q0[j] = hilbert_weight_parts(omx, opx, ax.a, ax.b) / E.rec.sqrt_mu0;
+    if (E.Nc > 0 || ax.kind == 2) E.q0[j] = hilbert_weight_parts(omx, opx, ax.a, ax.b) / E.rec.sqrt_mu0;
 }
 
 // Everything after the points: bin table, direct block, DFT phases and the
@@ -725,10 +727,14 @@ static void finish_axis(AxisPlan &ax, Evaluator &E, const PlanOptions &opt)
         ax.max_per_bin = std::max(ax.max_per_bin, ax.binptr[m + 1]);
         ax.binptr[m + 1] += ax.binptr[m];
     }
-    // direct block
+    // direct block: the low degrees of the first-kind functions, or of the
+    // second-kind ones (the imaginary part of W B before the DFT phase)
     ax.WV.assign((size_t)ax.nu0 * n, 0.0);
+    const bool second = ax.kind == 2;
     parallel_for(n, [&](int j) {
-        E.walk(j, ax.nu0 - 1, [&](int k, ld p, ld) { ax.WV[(size_t)k * n + j] = (double)(E.sw[j] * p); });
+        E.walk(j, ax.nu0 - 1, [&](int k, ld p, ld q) {
+            ax.WV[(size_t)k * n + j] = (double)(second ? E.sw[j] * q * E.invpw[j] : E.sw[j] * p);
+        });
     });
     // DFT phase table of eq. (45): exp(-2 pi i p / L), exact integer phase
     E.ph.resize(L);
@@ -739,6 +745,10 @@ static void finish_axis(AxisPlan &ax, Evaluator &E, const PlanOptions &opt)
     E.dbl_cols = ax.tol >= 1e-10;
     if (E.Nc > 0)
         rsvd(E, ax.tol, opt, ax.seed, ax);
+    // second kind: Im(u y) = Re((-i u) y), so the same kernels apply the
+    // second-kind transform once u is turned by -i (forward and transpose)
+    if (second)
+        for (cd &z : ax.U) z = cd(z.imag(), -z.real());
 }
 
 void build_axis(AxisPlan &ax, int n, double a, double b, double tol, const PlanOptions &opt)

@@ -316,3 +316,40 @@ def test_wide_direct_block_many_lines(jt, orc, n, nu0):
             for i in range(items):
                 ref = (A0 if direction == jt.FORWARD else A0.T) @ rows[i] @ mat
                 assert relerr(got[i], ref) <= 1e-11, (split, direction, i)
+
+
+# ------------------------------------------------------------------ (a, b) beyond (-1/2, 1/2)
+# The paper's analysis covers (-1/2, 1/2) and its experiments run (-1, 1)
+# (Section 4.2.1, the rank tables at a = b up to +-0.9; the stability table at
+# +-0.75).  There (1/4 - a^2) changes sign and the companion's weight exponents
+# approach -1; the transform is still checked against the oracle element by
+# element at the same bars.
+WIDE_AB = [((0.6, 0.7),), ((-0.8, 0.9),), ((0.9, -0.95),), ((-0.9, -0.9),), ((0.95, 0.95),), ((-0.99, 0.5),)]
+
+
+@pytest.mark.parametrize("ab", WIDE_AB)
+@pytest.mark.parametrize("n", [300, 1024, 4096])
+def test_wide_parameters_1d(jt, orc, ab, n):
+    A = orc.matrix(n, *ab[0])[0]
+    al = np.random.default_rng(n).standard_normal(n)
+    for prec in (0, 1):
+        tol = 1e-12 if prec == 0 else 1e-7
+        plan = plan_for(jt, (n,), ab, tol)
+        g = run(jt, plan, al, "fwd", prec)
+        assert relerr(g, A @ al) <= bound(prec, tol, 1), (prec, relerr(g, A @ al), plan.info(0))
+        a2 = run(jt, plan, A @ al, "inv", prec)
+        assert relerr(a2, al) <= bound(prec, tol, 1), (prec, relerr(a2, al))
+    orc.clear_cache()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_wide_parameters_2d_and_3d(jt, orc, prec):
+    tol = 1e-12 if prec == 0 else 1e-7
+    for shape, ab in (((512, 700), ((0.9, -0.8), (-0.95, 0.6))), ((64, 96, 130), ((0.75, 0.75), (-0.75, -0.75), (0.8, -0.9)))):
+        plan = plan_for(jt, shape, ab, tol)
+        al = np.random.default_rng(sum(shape)).standard_normal(shape)
+        g = run(jt, plan, al, "fwd", prec)
+        g_ref = orc.forward(al, ab)
+        assert relerr(g, g_ref) <= bound(prec, tol, len(shape)), (shape, prec, relerr(g, g_ref))
+        a2 = run(jt, plan, g_ref, "inv", prec)
+        assert relerr(a2, al) <= bound(prec, tol, len(shape)), (shape, prec, relerr(a2, al))
