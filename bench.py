@@ -34,7 +34,8 @@ sys.path.insert(0, ROOT)
 import workloads  # noqa: E402
 
 PEAK_FP64 = 78.6e12   # MI355X fp64 vector, FLOP/s
-PEAK_FP32 = 157.3e12  # MI355X fp32 vector, FLOP/s (packed); unpacked issue reaches half of it
+PEAK_FP32 = 157.3e12  # MI355X fp32 vector (packed; unpacked issue reaches half of it) and fp32 matrix, FLOP/s
+PEAK_HBM = 8000.0     # MI355X HBM3E, GB/s
 
 
 def axis_flops(n: int, L: int, nu0: int, rank: int, lines: int) -> float:
@@ -82,11 +83,11 @@ def measured_batch_traffic(workload: str, items: int):
     return float(rec["hbm_bytes"])
 
 
-def measured_traffic(kernel_prefix: str):
-    """HBM bytes per launch of the given kernel family from the committed
-    rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when the kernel source
-    changed after the counters were taken."""
-    prof = os.path.join(ROOT, "profiles", "axis_pass_2d_n1024_traffic.json")
+def measured_traffic(kernel_prefix: str, workload: str = "2d_n1024"):
+    """HBM bytes per launch of the given kernel family on the given workload
+    from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when
+    the kernel source changed after the counters were taken."""
+    prof = os.path.join(ROOT, "profiles", "axis_pass_%s_traffic.json" % workload)
     try:
         rec = json.load(open(prof))
         h = kernel_source_hash()
@@ -200,7 +201,9 @@ def workload_3d(args) -> int:
                      "rel_l2_forward": float(np.linalg.norm(gg - g_ref) / np.linalg.norm(g_ref)),
                      "rel_l2_roundtrip": float(np.linalg.norm(bb - al_np) / np.linalg.norm(al_np)),
                      "roofline": {"bound": "alu", "achieved": ach, "peak": peak / 1e12, "unit": "TFLOP/s",
-                                  "frac": ach / (peak / 1e12), "traffic": None,
+                                  "frac": ach / (peak / 1e12),
+                                  "traffic": measured_traffic("axis_pass<%s, 8" % ("float" if name == "fp32"
+                                                                                   else "double"), "3d_n256"),
                                   "kernel": "axis_pass<%s,8>" % ("float" if name == "fp32" else "double"),
                                   "flops_per_launch": float(np.mean(flops))}}
     cpu = None
@@ -302,7 +305,9 @@ def workload_1d(args) -> int:
                        "step": "one forward transform (1 axis-pass launch)"},
             "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"], "rel_l2_forward": head["rel_l2_forward"],
             "roofline": {"bound": "hbm", "achieved": head["hbm_gbs"], "peak": 8000.0, "unit": "GB/s",
-                         "frac": head["hbm_gbs"] / 8000.0, "traffic": None, "kernel": "axis_pass<double,10>",
+                         "frac": head["hbm_gbs"] / 8000.0,
+                         "traffic": measured_traffic("axis_pass<double, 10, 1, 1", "1d_n1024"),
+                         "kernel": "axis_pass<double,10,1,1>",
                          "bytes_per_launch": head["bytes_per_launch"],
                          "note": "a single line: launch latency, not bandwidth, bounds it"},
             "cpu_baseline": cpu, "fp64": head, "fp32": res["fp32"]}
@@ -374,14 +379,33 @@ def batched(args) -> int:
     torch.cuda.synchronize()
     ms = [a.elapsed_time(b) for a, b in ms]
     t_ms = float(np.mean(ms))
-    # algorithmic bytes: every pass streams its factors once and its lines in and out (fp32)
-    nbytes = 0.0
+    # algorithmic work: every pass streams its factors (or its dense matrix)
+    # once and its lines in and out (fp32); FFT passes do axis_flops on the
+    # vector units, dense passes 2 n^2 flops per line on the matrix cores
+    nbytes = fft_flops = mfma_flops = 0.0
     for p, s in zip(plans, shapes):
         total = int(np.prod(s))
         for ax in range(p.d):
             inf = p.info(ax)
-            nbytes += factor_bytes_fp32(inf, total // inf["n"]) + 8.0 * total
-    achieved = nbytes / (t_ms * 1e-3) / 1e9
+            lines = total // inf["n"]
+            if inf["nu0"] == inf["n"]:
+                nbytes += 4.0 * inf["n"] * inf["n"] + 8.0 * total
+                mfma_flops += 2.0 * inf["n"] * inf["n"] * lines
+            else:
+                nbytes += factor_bytes_fp32(inf, lines) + 8.0 * total
+                fft_flops += axis_flops(inf["n"], inf["L"], inf["nu0"], inf["rank"], lines)
+    t_s = t_ms * 1e-3
+    # the binding roofline is the one whose peak-rate time is longest
+    times = {"hbm": nbytes / (PEAK_HBM * 1e9), "mfma": mfma_flops / PEAK_FP32, "alu": fft_flops / PEAK_FP32}
+    bound = max(times, key=times.get)
+    fracs = {"hbm": nbytes / t_s / (PEAK_HBM * 1e9), "mfma": mfma_flops / t_s / PEAK_FP32,
+             "alu": fft_flops / t_s / PEAK_FP32}
+    if bound == "hbm":
+        roof = {"bound": "hbm", "achieved": nbytes / t_s / 1e9, "peak": PEAK_HBM, "unit": "GB/s"}
+    else:
+        fl = mfma_flops if bound == "mfma" else fft_flops
+        roof = {"bound": bound, "achieved": fl / t_s / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
     # accuracy on a sample of items against the oracle (outside the timed region)
     import oracle
 
@@ -422,9 +446,10 @@ def batched(args) -> int:
                    "units": info["units"], "grid": info["grid"], "threads": info["threads"],
                    "plan_seconds": t_plan, "graph": True, "tuning": tuning.get("source"),
                    "dense_items": int(sum(1 for p in plans if p.info(0)["nu0"] == p.info(0)["n"]))},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
-                     "frac": achieved / 8000.0, "traffic": measured_batch_traffic(args.workload, len(items)),
-                     "kernel": "batch_kernel<float>", "bytes_per_launch": nbytes},
+        "roofline": dict(roof, traffic=measured_batch_traffic(args.workload, len(items)),
+                         kernel="batch_kernel<float>", bytes_per_launch=nbytes, fft_flops_per_launch=fft_flops,
+                         mfma_flops_per_launch=mfma_flops, fracs=fracs,
+                         peak_times_ms={k: v * 1e3 for k, v in times.items()}),
         "sample_rel_l2_max": max(errs) if errs else None,
         "fp64_one_at_a_time": ({"ms": t64, "value": coeffs_sel / (t64 * 1e-3), "items": len(sel),
                                 "launches": int(sum(len(shapes[i]) for i in sel))} if sel else None),

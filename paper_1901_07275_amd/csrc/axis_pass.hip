@@ -48,8 +48,24 @@ __device__ __forceinline__ unsigned block_line(unsigned lpb)
 // lines (rank split, only for lines held by a single wave).  WIDE: blocks of
 // up to eight single-wave groups, for passes with too few lines to fill the
 // chip (a 1D transform is one line), where more groups per line shorten it.
+// Waves per SIMD the single-wave-line kernels are compiled for (1: as many
+// registers as the compiler wants).
+#ifndef JT_F32_FWD_MIN_WAVES
+#define JT_F32_FWD_MIN_WAVES 1
+#endif
+#ifndef JT_F32_INV_MIN_WAVES
+#define JT_F32_INV_MIN_WAVES 1
+#endif
+template <class T, int LOG2L, int FWD>
+constexpr int min_waves()
+{
+    if constexpr (Geo<LOG2L>::BLOCK > 64 || sizeof(T) == 8) return 1;
+    else return FWD ? JT_F32_FWD_MIN_WAVES : JT_F32_INV_MIN_WAVES;
+}
+
 template <class T, int LOG2L, int FWD, int WIDE>
-__global__ void __launch_bounds__(WIDE ? 512 : (Geo<LOG2L>::BLOCK == 64 ? 256 : Geo<LOG2L>::BLOCK))
+__global__ void __launch_bounds__(WIDE ? 512 : (Geo<LOG2L>::BLOCK == 64 ? 256 : Geo<LOG2L>::BLOCK),
+                                  (WIDE ? 1 : min_waves<T, LOG2L, FWD>()))
     axis_pass(AxisLaunch a)
 {
     using G = Geo<LOG2L>;

@@ -12,8 +12,13 @@ namespace jt {
 namespace dev {
 
 
+// Aligned to its size, so that LDS and global accesses of one complex value
+// are single 8- or 16-byte operations with immediate offsets.
+#ifndef JT_CPX_ALIGN
+#define JT_CPX_ALIGN 1
+#endif
 template <class T>
-struct cpx {
+struct alignas(JT_CPX_ALIGN ? 2 * sizeof(T) : sizeof(T)) cpx {
     T x, y;
 };
 
@@ -63,6 +68,47 @@ __device__ __forceinline__ cpx<T> w16(cpx<T> a)
         constexpr T c = (T)kW16c[e], s = (T)kW16s[e];
         return {c * a.x - s * a.y, s * a.x + c * a.y};
     }
+}
+
+// a * exp(2 pi i e / 16) for an e that is known after unrolling
+template <class T>
+__device__ __forceinline__ cpx<T> rot16(cpx<T> a, int e)
+{
+    switch (e & 15) {
+    case 0: return a;
+    case 1: return w16<T, 1>(a);
+    case 2: return w16<T, 2>(a);
+    case 3: return w16<T, 3>(a);
+    case 4: return w16<T, 4>(a);
+    case 5: return w16<T, 5>(a);
+    case 6: return w16<T, 6>(a);
+    case 7: return w16<T, 7>(a);
+    case 8: return w16<T, 8>(a);
+    case 9: return w16<T, 9>(a);
+    case 10: return w16<T, 10>(a);
+    case 11: return w16<T, 11>(a);
+    case 12: return w16<T, 12>(a);
+    case 13: return w16<T, 13>(a);
+    case 14: return w16<T, 14>(a);
+    default: return w16<T, 15>(a);
+    }
+}
+
+// The value itself, hidden from the optimiser (an empty asm statement that
+// claims to change it): twiddles derived from it are then recomputed in every
+// pass instead of being hoisted out of the term loop, where the 27 derived
+// factors of a 1024-point FFT would hold 108 extra registers in fp64.
+template <class T>
+__device__ __forceinline__ cpx<T> opaque(cpx<T> a)
+{
+    asm volatile("" : "+v"(a.x), "+v"(a.y));
+    return a;
+}
+
+template <class T>
+__device__ __forceinline__ cpx<T> csq(cpx<T> a)
+{
+    return {a.x * a.x - a.y * a.y, (T)2 * a.x * a.y};
 }
 
 template <class T>
@@ -233,39 +279,66 @@ struct Geo {
 // the fp32 kernels keep them in registers for the whole kernel; the fp64
 // kernels (twice the register cost) and blocks of 512+ threads read them from
 // the L-entry table when a pass needs them.
-// Where the per-pass twiddles live: 0 = registers (loaded once), 1 = a copy
-// of the table in LDS (loaded once per block), 2 = the table in global memory
-// (L1/L2 resident).  Measured (one-pass kernel, 1024- and 256-point lines):
-// fp64 is fastest from global memory in both directions; fp32 inverse passes
-// from registers (their direct block leaves registers free at that point);
-// fp32 forward passes from LDS on short lines and from global memory on
-// 1024-point lines.
+// Where the per-pass twiddles come from: 0 = registers (loaded once), 1 = a
+// copy of the table in LDS (loaded once per block), 2 = the table in global
+// memory (L1/L2 resident), 3 = computed in registers from two values per lane
+// loaded once: the twiddles of a radix-16 pass are the powers w^r (r < 16) of
+// one root of unity w per lane, built by squarings and products (at most four
+// roundings deep), and those of the final radix-2/4/8 pass are b^r times a
+// sixteenth root of unity known at compile time, with b = exp(2 pi i p / L).
+// Loading a twiddle per factor held the fp64 kernels at 256 registers, where
+// the compiler issues each load and waits for it before the next (27
+// round trips to L1/L2 per FFT); mode 3 needs no loads after the first and
+// frees the registers that held the 27 load addresses.
 #ifndef JT_TW_MODE_F64
-#define JT_TW_MODE_F64 2
+#define JT_TW_MODE_F64 3
+#endif
+#ifndef JT_TW_MODE_F32_FWD
+#define JT_TW_MODE_F32_FWD 3
+#endif
+// fp64 lines of up to 256 points (one radix-16 pass after the first, many
+// lines per pass): measured on 256^3, forward passes are fastest with the
+// twiddles from global memory (532 against 980 us per pass), inverse passes
+// with computed ones (1081 against 1130 us).
+#ifndef JT_TW_MODE_F64_SHORT_FWD
+#define JT_TW_MODE_F64_SHORT_FWD 2
+#endif
+#ifndef JT_TW_MODE_F64_SHORT_INV
+#define JT_TW_MODE_F64_SHORT_INV 3
 #endif
 template <class T, int LOG2L, int FWD>
 constexpr int tw_mode()
 {
-    if constexpr (Geo<LOG2L>::BLOCK > 256) return 2;  // big lines: too few registers per lane
-    else if constexpr (sizeof(T) == 8) return JT_TW_MODE_F64;
+    if constexpr (sizeof(T) == 8)
+        return LOG2L <= 8 ? (FWD ? JT_TW_MODE_F64_SHORT_FWD : JT_TW_MODE_F64_SHORT_INV) : JT_TW_MODE_F64;
+    else if constexpr (Geo<LOG2L>::BLOCK > 256) return 3;  // big lines: too few registers per lane
     else if constexpr (!FWD) return 0;
-    else return LOG2L <= 8 ? 1 : 2;
+    else return LOG2L <= 8 ? 1 : JT_TW_MODE_F32_FWD;
 }
 
 template <class T, int LOG2L, int FWD>
 struct Twiddles {
     using G = Geo<LOG2L>;
-    static constexpr bool kHoist = tw_mode<T, LOG2L, FWD>() == 0;
+    static constexpr int kMode = tw_mode<T, LOG2L, FWD>();
+    static constexpr bool kHoist = kMode == 0;
+    static constexpr bool kComp = kMode == 3;
     cpx<T> mid_[(kHoist && G::NMID > 0) ? G::NMID : 1][15];
     cpx<T> fin_[(kHoist && G::RF > 1) ? 16 / G::RF : 1][(G::RF > 1) ? G::RF - 1 : 1];
+    cpx<T> wb_[(kComp && G::NMID > 0) ? G::NMID : 1];  // root of pass i+1: omega_{16 Ns}^{p mod Ns}
+    cpx<T> fb_;                                         // omega_L^p (final pass)
     const cpx<T> *tw;
     int p;
 
-    // pass i+1 has Ns = 16^(i+1); factor omega_{16 Ns}^{(p mod Ns) r} = tw[(p mod Ns) r L / (16 Ns)]
-    static __device__ __forceinline__ int mid_index(int i, int r, int p)
+    static __device__ __forceinline__ constexpr int pass_ns(int i)
     {
         int ns = 16;
         for (int k = 0; k < i; ++k) ns *= 16;
+        return ns;
+    }
+    // pass i+1 has Ns = 16^(i+1); factor omega_{16 Ns}^{(p mod Ns) r} = tw[(p mod Ns) r L / (16 Ns)]
+    static __device__ __forceinline__ int mid_index(int i, int r, int p)
+    {
+        const int ns = pass_ns(i);
         return (p & (ns - 1)) * r * (G::L / (16 * ns));
     }
     // final pass (radix RF, Ns = L/RF): task j = p + P t, factor omega_L^{j r}
@@ -287,6 +360,11 @@ struct Twiddles {
                     for (int r = 1; r < G::RF; ++r) fin_[t][r - 1] = tw[fin_index(t, r, p)];
             }
         }
+        if constexpr (kComp) {
+#pragma unroll
+            for (int i = 0; i < G::NMID; ++i) wb_[i] = tw[mid_index(i, 1, p)];
+            if constexpr (G::RF > 1) fb_ = tw[p];
+        }
     }
     __device__ __forceinline__ cpx<T> mid(int i, int r) const
     {
@@ -297,6 +375,54 @@ struct Twiddles {
     {
         if constexpr (kHoist) return fin_[t][r - 1];
         else return tw[fin_index(t, r, p)];
+    }
+    // v[r] *= (twiddle of pass i+1, factor r) for r = 1..15
+    __device__ __forceinline__ void apply_mid(int i, cpx<T> *v) const
+    {
+        if constexpr (kComp) {
+            const cpx<T> w1 = opaque(wb_[i]), w2 = csq(w1), w3 = cmul(w2, w1), w4 = csq(w2);
+            const cpx<T> w8 = csq(w4), w12 = cmul(w8, w4);
+            v[1] = cmul(v[1], w1);
+            v[2] = cmul(v[2], w2);
+            v[3] = cmul(v[3], w3);
+            v[4] = cmul(v[4], w4);
+            v[8] = cmul(v[8], w8);
+            v[12] = cmul(v[12], w12);
+            v[5] = cmul(v[5], cmul(w4, w1));
+            v[6] = cmul(v[6], cmul(w4, w2));
+            v[7] = cmul(v[7], cmul(w4, w3));
+            v[9] = cmul(v[9], cmul(w8, w1));
+            v[10] = cmul(v[10], cmul(w8, w2));
+            v[11] = cmul(v[11], cmul(w8, w3));
+            v[13] = cmul(v[13], cmul(w12, w1));
+            v[14] = cmul(v[14], cmul(w12, w2));
+            v[15] = cmul(v[15], cmul(w12, w3));
+        } else {
+#pragma unroll
+            for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], mid(i, r));
+        }
+    }
+    // powers b^r (r < RF) of the final pass's per-lane root (mode 3 only)
+    __device__ __forceinline__ void fin_powers(cpx<T> *bp) const
+    {
+        if constexpr (kComp && G::RF > 1) {
+            bp[1] = opaque(fb_);
+#pragma unroll
+            for (int r = 2; r < G::RF; ++r) bp[r] = (r % 2 == 0) ? csq(bp[r / 2]) : cmul(bp[r - 1], bp[1]);
+        }
+    }
+    // w[r] *= (twiddle of task t, factor r) for r = 1..RF-1
+    __device__ __forceinline__ void apply_fin(int t, cpx<T> *w, const cpx<T> *bp) const
+    {
+#pragma unroll
+        for (int r = 1; r < G::RF; ++r) {
+            if constexpr (kComp) {
+                // omega_L^{(p + P t) r} = b^r omega_16^{t r}  (P = L / 16)
+                w[r] = cmul(w[r], rot16(bp[r], t * r));
+            } else {
+                w[r] = cmul(w[r], fin(t, r));
+            }
+        }
     }
 };
 
@@ -325,8 +451,7 @@ __device__ __forceinline__ void fft_line(cpx<T> (*v)[16], cpx<T> *buf, const int
         for (int h = 0; h < VL; ++h) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) v[h][r] = buf[pad(pv[h] + r * G::P)];
-#pragma unroll
-            for (int r = 1; r < 16; ++r) v[h][r] = cmul(v[h][r], tw[h].mid(i, r));
+            tw[h].apply_mid(i, v[h]);
             dft16(v[h]);
         }
         const bool last = (G::RF == 1) && (i == G::NMID - 1);
@@ -347,14 +472,15 @@ __device__ __forceinline__ void fft_line(cpx<T> (*v)[16], cpx<T> *buf, const int
         sync_line<G::TPL>();
 #pragma unroll
         for (int h = 0; h < VL; ++h) {
+            cpx<T> bp[RF];
+            tw[h].fin_powers(bp);
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 cpx<T> w[RF];
                 const int j = pv[h] + G::P * t;
 #pragma unroll
                 for (int r = 0; r < RF; ++r) w[r] = buf[pad(j + r * (G::L / RF))];
-#pragma unroll
-                for (int r = 1; r < RF; ++r) w[r] = cmul(w[r], tw[h].fin(t, r));
+                tw[h].apply_fin(t, w, bp);
                 dftR<T, RF>(w);
                 // output index j + r * (L/RF) = p + P (t + r * NT)
 #pragma unroll
@@ -406,7 +532,31 @@ __device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, 
 
     // the line, in the lane-owned layout (zero beyond n); dtype branch is uniform
     T x[VL][16];
-    if (a.in_f64) {
+#ifndef JT_SHARED_STRIDED_LOAD
+#define JT_SHARED_STRIDED_LOAD 1
+#endif
+    if (JT_SHARED_STRIDED_LOAD && VL == 1 && S > 1 && stride > 1u) {
+        // Strided line: every element is its own cache line, so the S split
+        // groups that share the line each load a 1/S share (the slots they
+        // also store) into group 0's line buffer, and all of them read the
+        // whole line back from there.  Uniform branch; block barriers.
+        T *stage = reinterpret_cast<T *>(smem + slot * G::BUF);
+        __syncthreads();  // the buffer's previous users are done
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            if (q % S != sgrp) continue;
+            const int k = pv[0] + G::P * q;
+            T v = (T)0;
+            if (active && k < n)
+                v = a.in_f64 ? (T) reinterpret_cast<const double *>(a.in)[base + (unsigned)k * stride]
+                             : (T) reinterpret_cast<const float *>(a.in)[base + (unsigned)k * stride];
+            stage[k] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 16; ++q) x[0][q] = stage[pv[0] + G::P * q];
+        __syncthreads();  // group 0 reuses the buffer from here on
+    } else if (a.in_f64) {
         const double *src = reinterpret_cast<const double *>(a.in);
 #pragma unroll
         for (int h = 0; h < VL; ++h)
@@ -488,7 +638,10 @@ __device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, 
 #define JT_HOIST_F64 1
 #endif
         // (fp64 only from 512 points: measured slower on 256-point lines)
-        constexpr bool kHB = JT_HOIST_BINS && Geo<LOG2L>::BLOCK <= 256 && (sizeof(T) == 4 || (JT_HOIST_F64 && LOG2L >= 9));
+#ifndef JT_HB_F64_MIN
+#define JT_HB_F64_MIN 9
+#endif
+        constexpr bool kHB = JT_HOIST_BINS && Geo<LOG2L>::BLOCK <= 256 && (sizeof(T) == 4 || (JT_HOIST_F64 && LOG2L >= JT_HB_F64_MIN));
         int bix[VL][kHB ? 16 : 1];
         if constexpr (kHB) {
 #pragma unroll

@@ -195,6 +195,30 @@ static void newton_double_group(const Rec &r, int n, int cnt, double *t, const d
     }
 }
 
+// Christoffel weights in double for up to 8 roots at once,
+// 1 / omega = sum_{k<n} phat_k(x)^2 (a sum of positive terms: no cancellation
+// next to x = +-1).  For plans whose tolerance is far above the double
+// precision node error.
+static void weights_double_group(const Rec &r, int n, int cnt, const double *t, double *w)
+{
+    constexpr int G = 8;
+    const double p0 = (double)(1 / r.sqrt_mu0);
+    double x[G], pm[G], p[G], s[G];
+    for (int i = 0; i < G; ++i) {
+        x[i] = (i < cnt) ? std::cos(t[i]) : 0.0;
+        pm[i] = 0; p[i] = p0; s[i] = 0;
+    }
+    for (int k = 0; k < n; ++k) {
+        const double ip = r.ibe_d[k + 1], al = r.al_d[k], bk = r.be_d[k];
+        for (int i = 0; i < G; ++i) {
+            s[i] += p[i] * p[i];
+            const double pn = ((x[i] - al) * p[i] - bk * pm[i]) * ip;
+            pm[i] = p[i]; p[i] = pn;
+        }
+    }
+    for (int i = 0; i < cnt; ++i) w[i] = 1.0 / s[i];
+}
+
 // One long double Newton step from a root already accurate to double
 // precision, returning the Gauss-Jacobi weight as well.  The weight is the
 // reciprocal of F(x) = sum_{k<n} p_k(x)^2 = be_n (p_n' p_{n-1} - p_{n-1}' p_n)
@@ -245,7 +269,10 @@ static bool newton_root(const Rec &r, int n, ld &t, ld lo, ld hi, bool near = fa
     return false;
 }
 
-static void nodes_ld(const Rec &r, int n, ld a, ld b, std::vector<ld> &t, std::vector<ld> &om)
+// refine: finish every root with one long double Newton step (tolerances
+// near double rounding); otherwise the double Newton roots and double
+// Christoffel-Darboux weights are kept.
+static void nodes_ld(const Rec &r, int n, ld a, ld b, std::vector<ld> &t, std::vector<ld> &om, bool refine = true)
 {
     t.assign(n, 0);
     om.assign(n, 0);
@@ -265,7 +292,14 @@ static void nodes_ld(const Rec &r, int n, ld a, ld b, std::vector<ld> &t, std::v
             td[i] = (double)tj; lod[i] = (double)lo; hid[i] = (double)hi;
         }
         newton_double_group(r, n, cnt, td, lod, hid, conv);
+        double wd[8];
+        if (!refine) weights_double_group(r, n, cnt, td, wd);
         for (int i = 0; i < cnt; ++i) {
+            if (!refine && conv[i] && wd[i] > 0 && std::isfinite(wd[i])) {
+                t[j0 + i] = td[i];
+                om[j0 + i] = wd[i];
+                continue;
+            }
             ld tj = conv[i] ? (ld)td[i] : tl[i];
             ld w = 0;
             if (conv[i] && newton_final(r, n, a, b, tj, w) && tj > lol[i] && tj < hil[i]) {
@@ -377,49 +411,54 @@ const QuadTables &quad_tables()
     return t;
 }
 
-// integral over v in [0, ell] of expm1(e_far*log((ell-v)/ell) + e_near*log1p(v/delta)) / v
-ld half_integral(ld e_far, ld e_near, ld ell, ld delta)
+// integral over v in [0, ell] of expm1(e_far*log((ell-v)/ell) + e_near*log1p(v/delta)) / v,
+// in long double (F = ld) or, for plans whose tolerance is far above double
+// rounding, in double (F = double): the rank needs the companion only to well
+// below the tolerance, and the transform does not depend on it.
+template <class F>
+F half_integral(F e_far, F e_near, F ell, F delta)
 {
     const QuadTables &T = quad_tables();
-    auto phi = [&](ld v, ld ellmv) -> ld {
-        ld lf = (v < 0.5L * ell) ? log1pl(-v / ell) : logl(ellmv / ell);
-        ld lam = e_far * lf + e_near * log1pl(v / delta);
-        return expm1l(lam) / v;
+    auto phi = [&](F v, F ellmv) -> F {
+        F lf = (v < F(0.5) * ell) ? std::log1p(-v / ell) : std::log(ellmv / ell);
+        F lam = e_far * lf + e_near * std::log1p(v / delta);
+        return std::expm1(lam) / v;
     };
-    ld sum = 0;
-    ld d = 0;
+    F sum = 0;
+    F d = 0;
     for (;;) {
-        ld nxt = 2 * d + delta;
-        if (nxt > 0.5L * ell) break;
-        ld c = 0.5L * (d + nxt), h = 0.5L * (nxt - d);
+        F nxt = 2 * d + delta;
+        if (nxt > F(0.5) * ell) break;
+        F c = F(0.5) * (d + nxt), h = F(0.5) * (nxt - d);
         for (int i = 0; i < 16; ++i) {
-            ld v = c + h * T.gl_x[i];
-            sum += h * T.gl_w[i] * phi(v, ell - v);
+            F v = c + h * (F)T.gl_x[i];
+            sum += h * (F)T.gl_w[i] * phi(v, ell - v);
         }
         d = nxt;
     }
-    const ld len = ell - d;
+    const F len = ell - d;
     for (size_t k = 0; k < T.ts_tau.size(); ++k) {
-        ld v = d + len * T.ts_tau[k];
-        ld ellmv = len * T.ts_ctau[k];
+        F v = d + len * (F)T.ts_tau[k];
+        F ellmv = len * (F)T.ts_ctau[k];
         if (!(v > 0) || !(ellmv > 0)) continue;
-        sum += len * T.ts_w[k] * phi(v, ellmv);
+        sum += len * (F)T.ts_w[k] * phi(v, ellmv);
     }
     return sum;
 }
 
-ld hilbert_weight_parts(ld omx, ld opx, ld a, ld b)
+template <class F>
+F hilbert_weight_parts(F omx, F opx, F a, F b)
 {
-    ld wx = powl(omx, a) * powl(opx, b);
-    ld right = half_integral(a, b, omx, opx);
-    ld left = half_integral(b, a, opx, omx);
-    return wx * (logl(omx / opx) + right - left);
+    F wx = std::pow(omx, a) * std::pow(opx, b);
+    F right = half_integral<F>(a, b, omx, opx);
+    F left = half_integral<F>(b, a, opx, omx);
+    return wx * (std::log(omx / opx) + right - left);
 }
 }  // namespace
 
 long double hilbert_weight(long double x, long double a, long double b)
 {
-    return hilbert_weight_parts(1 - x, 1 + x, a, b);
+    return hilbert_weight_parts<ld>(1 - x, 1 + x, a, b);
 }
 
 // ------------------------------------------------------------------ matrix W B
@@ -548,23 +587,46 @@ static void rsvd(const Evaluator &E, double tol, const PlanOptions &opt, uint64_
     double zc2 = 0.0;
     for (const cd &z : Zc.a) zc2 += std::norm(z);
 
-    auto rel_error = [&](const CMat &U0, const std::vector<double> &s, const CMat &Vh, int rk) {
-        double e2 = 0.0;
-        std::vector<double> part(check_rows.size(), 0.0);
-        parallel_for((int)check_rows.size(), [&](int i) {
-            int j = check_rows[i];
-            std::vector<cd> coef(rk);
-            for (int l = 0; l < rk; ++l) coef[l] = U0(j, l) * s[l];
-            double acc = 0.0;
-            for (int c = 0; c < Nc; ++c) {
-                cd v(0.0, 0.0);
-                for (int l = 0; l < rk; ++l) v += coef[l] * Vh(l, c);
-                acc += std::norm(Zc(i, c) - v);
+    // Relative Frobenius error of U0 diag(s) Vh on the check rows, truncated
+    // to the first `keep` terms and with all rk terms, in one pass over the
+    // columns (each column of the check rows and of Vh is contiguous).  The
+    // per-chunk partial sums are added in chunk order, so the result does not
+    // depend on the thread count.
+    auto rel_errors = [&](const CMat &U0, const std::vector<double> &s, const CMat &Vh, int rk, int keep) {
+        const int nchk = (int)check_rows.size();
+        CMat C(nchk, rk);
+        for (int l = 0; l < rk; ++l)
+            for (int i = 0; i < nchk; ++i) C(i, l) = U0(check_rows[i], l) * s[l];
+        constexpr int kChunk = 64;
+        const int nchunk = (Nc + kChunk - 1) / kChunk;
+        std::vector<double> pk(nchunk, 0.0), pf(nchunk, 0.0);
+        parallel_for(nchunk, [&](int ch) {
+            std::vector<cd> res(nchk);
+            double ek = 0.0, ef = 0.0;
+            const int c1 = std::min(Nc, (ch + 1) * kChunk);
+            for (int c = ch * kChunk; c < c1; ++c) {
+                for (int i = 0; i < nchk; ++i) res[i] = Zc(i, c);
+                for (int l = 0; l < rk; ++l) {
+                    if (l == keep)
+                        for (int i = 0; i < nchk; ++i) ek += std::norm(res[i]);
+                    const cd vl = Vh(l, c);
+                    const cd *cl = &C.a[(size_t)l * nchk];
+                    for (int i = 0; i < nchk; ++i) res[i] -= cl[i] * vl;
+                }
+                double e = 0.0;
+                for (int i = 0; i < nchk; ++i) e += std::norm(res[i]);
+                ef += e;
+                if (keep >= rk) ek += e;
             }
-            part[i] = acc;
+            pk[ch] = ek;
+            pf[ch] = ef;
         });
-        for (double p : part) e2 += p;
-        return std::sqrt(e2 / zc2);
+        double e2k = 0.0, e2f = 0.0;
+        for (int ch = 0; ch < nchunk; ++ch) {
+            e2k += pk[ch];
+            e2f += pf[ch];
+        }
+        return std::make_pair(std::sqrt(e2k / zc2), std::sqrt(e2f / zc2));
     };
 
     for (int round = 0;; ++round) {
@@ -619,7 +681,6 @@ static void rsvd(const Evaluator &E, double tol, const PlanOptions &opt, uint64_
         CMat U0 = matmul(Qcol, UM);
         CMat Vh = matmul(adjoint(VM), adjoint(Qrow));
         const int rk = (int)s.size();
-        double err_full = rel_error(U0, s, Vh, rk);
         // truncate: drop the tail whose Frobenius mass is below tol/2
         double fro2 = 0.0;
         for (double v : s) fro2 += v * v;
@@ -631,9 +692,11 @@ static void rsvd(const Evaluator &E, double tol, const PlanOptions &opt, uint64_
             tail2 = t2;
             --keep;
         }
+        const auto errs = rel_errors(U0, s, Vh, rk, keep);
+        const double err_full = errs.second;
         bool last = (r >= rmax);
         if (err_full <= 0.5 * tol || last) {
-            double err = rel_error(U0, s, Vh, keep);
+            double err = errs.first;
             if (err > tol && keep < rk) {
                 keep = rk;
                 err = err_full;
@@ -685,6 +748,7 @@ static void start_axis(AxisPlan &ax, Evaluator &E, int n, double a, double b, do
     ax.seed = opt.seed ? opt.seed : mix_key(n, a, b, tol);
     ax.kind = opt.kind;
     E.n = n; E.nu0 = ax.nu0; E.L = L; E.Nc = n - ax.nu0;
+    E.dbl_cols = tol >= 1e-10;
     E.rec = recurrence(n + 1, a, b);
     E.x.resize(n); E.sw.resize(n); E.invpw.resize(n); E.q0.resize(n); E.m.resize(n);
     ax.t.resize(n); ax.x.resize(n); ax.omega.resize(n); ax.bins.resize(n);
@@ -706,7 +770,12 @@ static void set_point(AxisPlan &ax, Evaluator &E, int j, ld t, ld sw, ld om)
     ax.x[j] = (double)xj;
     ax.omega[j] = (double)om;
     ax.bins[j] = E.m[j];
-    if (E.Nc > 0 || ax.kind == 2) E.q0[j] = hilbert_weight_parts(omx, opx, ax.a, ax.b) / E.rec.sqrt_mu0;
+    // double quadrature only where the weight's exponents are mild: near -1
+    // the tanh-sinh tail of the far-end singularity overflows double range
+    const bool dbl_q = E.dbl_cols && ax.a > -0.5 && ax.b > -0.5;
+    if (E.Nc > 0 || ax.kind == 2)
+        E.q0[j] = (dbl_q ? (ld)hilbert_weight_parts<double>((double)omx, (double)opx, ax.a, ax.b)
+                         : hilbert_weight_parts<ld>(omx, opx, ax.a, ax.b)) / E.rec.sqrt_mu0;
 }
 
 // Everything after the points: bin table, direct block, DFT phases and the
@@ -742,7 +811,6 @@ static void finish_axis(AxisPlan &ax, Evaluator &E, const PlanOptions &opt)
         ld ang = -2 * kPi * p / L;
         E.ph[p] = cd((double)cosl(ang), (double)sinl(ang));
     }
-    E.dbl_cols = ax.tol >= 1e-10;
     if (E.Nc > 0)
         rsvd(E, ax.tol, opt, ax.seed, ax);
     // second kind: Im(u y) = Re((-i u) y), so the same kernels apply the
@@ -757,7 +825,10 @@ void build_axis(AxisPlan &ax, int n, double a, double b, double tol, const PlanO
     Evaluator E;
     start_axis(ax, E, n, a, b, tol, opt);
     std::vector<ld> tl, wl;
-    nodes_ld(E.rec, n, a, b, tl, wl);
+    // double-precision nodes and weights are kept at tolerances of 1e-7 and
+    // looser: their error (weights to about 3e-17 n^2 relative, from the
+    // double x next to +-1) stays two orders below such a tolerance
+    nodes_ld(E.rec, n, a, b, tl, wl, tol < 1e-7);
     // uniform transform: rows weighted by sqrt(omega_j) (Section 3.1, eq. (37))
     parallel_for(n, [&](int j) { set_point(ax, E, j, tl[j], sqrtl(wl[j]), wl[j]); });
     finish_axis(ax, E, opt);
@@ -797,7 +868,7 @@ void exact_entries(const AxisPlan &ax, int count, const int *rows, const int *de
         ld sh = sinl(t / 2), ch = cosl(t / 2);
         ld omx = 2 * sh * sh, opx = 2 * ch * ch;
         ld wx = powl(omx, (ld)ax.a) * powl(opx, (ld)ax.b);
-        ld q = hilbert_weight_parts(omx, opx, ax.a, ax.b) / rec.sqrt_mu0;
+        ld q = hilbert_weight_parts<ld>(omx, opx, ax.a, ax.b) / rec.sqrt_mu0;
         ld pm = 0, p = 1 / rec.sqrt_mu0, qm = 0;
         for (int kk = 0; kk < k; ++kk) {
             ld ib = rec.ibe[kk + 1];

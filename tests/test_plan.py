@@ -22,15 +22,19 @@ def plan1(n, a, b, tol, **kw):
                                    (1000, 0.25, -0.35), (1024, -0.4, 0.1), (4097, 0.45, -0.45),
                                    (300, 0.9, -0.9), (200, -0.75, 0.6)])
 def test_nodes_and_weights_match_oracle(orc, n, a, b):
-    P = plan1(n, a, b, 1e-7)
-    t, x, w = P.nodes(0)
     _, xo, wo = orc.matrix(n, a, b)
-    assert np.all(np.diff(t) > 0)
-    np.testing.assert_allclose(x, xo, rtol=0, atol=4e-16)
-    # weights at the end nodes, where 1 -+ x ~ 1/n^2, inherit the ~1e-19 absolute
-    # resolution of x in long double relative to 1 -+ x: allow 1e-12 relative
-    np.testing.assert_allclose(w, wo, rtol=1e-12, atol=0)
-    np.testing.assert_allclose(np.cos(t), x, rtol=0, atol=4e-16)
+    # tolerances below 1e-7: long double refinement.  Weights at the end
+    # nodes, where 1 -+ x ~ 1/n^2, inherit the ~1e-19 absolute resolution of x
+    # in long double relative to 1 -+ x: allow 1e-12 relative.
+    # Tolerances of 1e-7 and looser keep the double Newton roots and double
+    # Christoffel weights: x to rounding, weights to about 3e-17 n^2 relative
+    # (double x next to +-1), two orders below such a tolerance.
+    for tol, wtol in ((1e-8, 1e-12), (1e-7, max(1e-12, 3e-17 * n * n))):
+        t, x, w = plan1(n, a, b, tol).nodes(0)
+        assert np.all(np.diff(t) > 0)
+        np.testing.assert_allclose(x, xo, rtol=0, atol=4e-16)
+        np.testing.assert_allclose(w, wo, rtol=wtol, atol=0)
+        np.testing.assert_allclose(np.cos(t), x, rtol=0, atol=4e-16)
 
 
 @pytest.mark.parametrize("n,a,b", [(1024, 0.25, -0.35), (1000, 0.0, 0.0), (256, 0.3, 0.3)])
@@ -288,3 +292,15 @@ def test_multi_axis_plan_keeps_axis_parameters():
     P = jt.Plan([30, 70, 200], [(0.1, 0.2), (-0.3, 0.4), (0.45, -0.15)], 1e-9)
     assert [P.info(i)["n"] for i in range(3)] == [30, 70, 200]
     assert P.info(2)["L"] == 256 and P.info(1)["L"] == 128 and P.info(0)["L"] == 64
+
+
+@pytest.mark.parametrize("tol", [1e-7, 1e-12])
+@pytest.mark.parametrize("ab", [(0.6, 0.7), (-0.8, 0.9), (0.9, -0.95), (-0.9, -0.9), (0.95, 0.95), (-0.99, 0.5),
+                                (-0.5, -0.5), (0.45, -0.45), (0.0, 0.0)])
+def test_plans_are_finite_and_meet_the_tolerance_across_parameters(ab, tol):
+    """Every plan path (double or long double nodes, companion quadrature)
+    stays finite out to exponents of -0.99 and meets its tolerance."""
+    for n in (300, 2048):
+        inf = plan1(n, ab[0], ab[1], tol).info(0)
+        assert np.isfinite(inf["fro"]) and inf["fro"] > 0
+        assert inf["rel_err"] <= tol, (n, inf)
