@@ -353,3 +353,24 @@ def test_wide_parameters_2d_and_3d(jt, orc, prec):
         assert relerr(g, g_ref) <= bound(prec, tol, len(shape)), (shape, prec, relerr(g, g_ref))
         a2 = run(jt, plan, g_ref, "inv", prec)
         assert relerr(a2, al) <= bound(prec, tol, len(shape)), (shape, prec, relerr(a2, al))
+
+
+# ------------------------------------------------------------------ strided 1024-point passes
+# Strided passes over many 1024-point lines (rank split S > 1, the line shared
+# through LDS), with a line count that is not a multiple of the block's and
+# a nonzero outer index.
+@pytest.mark.parametrize("shape,axis", [((1000, 1030), 0), ((1024, 4, 300), 0), ((3, 1024, 401), 1)])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_strided_passes_of_long_lines(jt, orc, shape, axis, prec):
+    tol = 1e-12 if prec == 0 else 1e-7
+    ab = tuple([(0.25, -0.35), (-0.4, 0.1), (0.3, 0.3)][:len(shape)])
+    plan = plan_for(jt, shape, ab, tol)
+    dev = _dev()
+    x = np.random.default_rng(sum(shape)).standard_normal(shape)
+    A = orc.matrix(shape[axis], *ab[axis])[0]
+    xt = torch.from_numpy(x).to(dev)
+    for direction, M in ((jt.FORWARD, A), (jt.INVERSE, A.T)):
+        y = plan.apply_axis(axis, direction, xt, prec=prec)
+        torch.cuda.synchronize()
+        ref = np.moveaxis(np.tensordot(M, x, axes=([1], [axis])), 0, axis)
+        assert relerr(y.cpu().numpy(), ref) <= bound(prec, tol, 1), (shape, axis, direction)
