@@ -81,6 +81,17 @@ typedef struct {
                          Hilbert transform of w phat_k, i.e. the imaginary part of W B of
                          eq. (45) before the DFT phase.  A second-kind plan has only the
                          forward transform (its matrix is not orthogonal) */
+    int planner;      /* how the host finds the nodes, the weights and the sampled columns of
+                         Algorithm 2.1: 0 = automatic (phase functions from 1024 points on
+                         where they apply), 1 = the three-term recurrence throughout (exact
+                         evaluation, O(n^2)), 2 = the nonoscillatory phase and amplitude
+                         functions of Section 2.2 wherever they apply: uniform plans with
+                         |a|, |b| < 1/2 and tol >= 1e-8.  They are tabulated on the paper's
+                         piecewise Chebyshev grid by the third-order ODE for N = M^2 (eq.
+                         (phase:Neq)) and spectral integration of psi' = W / N, and read by
+                         barycentric interpolation (eq. (cheby:bary)); the nodes solve
+                         psi = pi/2 (mod pi) and the weights are pi / psi'.  Sampled rows
+                         and the direct block always come from the recurrence */
 } jt_plan_options;
 
 /* Per-axis facts about a plan. */
@@ -93,6 +104,8 @@ typedef struct {
     int rsvd_rounds;  /* rank-growth rounds Algorithm 2.1 needed */
     double rel_err;   /* measured ||W B - sum_l u_l v_l^T||_F / ||W B||_F */
     double fro;       /* ||W B||_F */
+    int planner;      /* 1: recurrence throughout; 2: phase functions gave the nodes, weights
+                         and sampled columns (jt_plan_options.planner) */
 } jt_axis_info;
 
 /*

@@ -52,13 +52,14 @@ _STATUS = {0: "JT_OK", 1: "JT_EINVAL", 2: "JT_ENOMEM", 3: "JT_EDEVICE", 4: "JT_E
 
 class PlanOptions(ctypes.Structure):
     _fields_ = [("nu0", ctypes.c_int), ("dense_below", ctypes.c_int), ("oversample", ctypes.c_int),
-                ("iterations", ctypes.c_int), ("seed", ctypes.c_uint64), ("kind", ctypes.c_int)]
+                ("iterations", ctypes.c_int), ("seed", ctypes.c_uint64), ("kind", ctypes.c_int),
+                ("planner", ctypes.c_int)]
 
 
 class AxisInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("L", ctypes.c_int), ("nu0", ctypes.c_int), ("rank", ctypes.c_int),
                 ("max_per_bin", ctypes.c_int), ("rsvd_rounds", ctypes.c_int),
-                ("rel_err", ctypes.c_double), ("fro", ctypes.c_double)]
+                ("rel_err", ctypes.c_double), ("fro", ctypes.c_double), ("planner", ctypes.c_int)]
 
 
 class BatchOptions(ctypes.Structure):
@@ -182,7 +183,7 @@ class Plan:
 
     def __init__(self, n: Sequence[int], ab: Sequence[Sequence[float]], tol: float,
                  nu0: int = 0, dense_below: int = -1, oversample: int = 0, iterations: int = 0,
-                 seed: int = 0, kind: int = 1):
+                 seed: int = 0, kind: int = 1, planner: int = 0):
         self.n = tuple(int(v) for v in n)
         self.ab = tuple((float(a), float(b)) for a, b in ab)
         if len(self.ab) != len(self.n):
@@ -192,7 +193,7 @@ class Plan:
         nn = (ctypes.c_int * d)(*self.n)
         aa = (ctypes.c_double * d)(*[p[0] for p in self.ab])
         bb = (ctypes.c_double * d)(*[p[1] for p in self.ab])
-        opt = PlanOptions(nu0, dense_below, oversample, iterations, seed, kind)
+        opt = PlanOptions(nu0, dense_below, oversample, iterations, seed, kind, planner)
         h = _vp()
         _check(_lib.jt_plan_ex(d, nn, aa, bb, self.tol, ctypes.byref(opt), ctypes.byref(h)))
         self._h = h
@@ -362,12 +363,12 @@ class Plan:
 
 
 # ---------------------------------------------------------------- many plans, batches
-def plan_many(shapes, abs_, tol: float, dense_below=None):
+def plan_many(shapes, abs_, tol: float, dense_below=None, planner: int = 0):
     """Build one plan per item on the host, one host thread per plan.
 
     shapes: per item a tuple of sizes (d = 1..3); abs_: per item a tuple of (a, b)
     pairs; dense_below: None, or per item the dense-path threshold (the
-    FFT-vs-direct crossover)."""
+    FFT-vs-direct crossover); planner: jt_plan_options.planner for every item."""
     count = len(shapes)
     dims = [len(s) for s in shapes]
     flat_n = [int(v) for s in shapes for v in s]
@@ -377,10 +378,11 @@ def plan_many(shapes, abs_, tol: float, dense_below=None):
         raise ValueError("need one (a, b) pair per axis of every item")
     handles = (_vp * count)()
     opts = None
-    if dense_below is not None:
+    if dense_below is not None or planner:
         arr = (PlanOptions * count)()
-        for i, db in enumerate(dense_below):
-            arr[i].dense_below = int(db)
+        for i in range(count):
+            arr[i].dense_below = -1 if dense_below is None else int(dense_below[i])
+            arr[i].planner = int(planner)
         opts = arr
     _check(_lib.jt_plan_many(count, (ctypes.c_int * count)(*dims), (ctypes.c_int * len(flat_n))(*flat_n),
                              (ctypes.c_double * len(flat_a))(*flat_a), (ctypes.c_double * len(flat_b))(*flat_b),

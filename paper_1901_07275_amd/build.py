@@ -24,7 +24,7 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wn
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics"]
 
-SOURCES = ["plan.cpp", "dense.cpp", "api.cpp", "queue.cpp", "batch_api.cpp", "server.cpp", "axis_pass.hip", "batch.hip"]
+SOURCES = ["plan.cpp", "phase.cpp", "dense.cpp", "api.cpp", "queue.cpp", "batch_api.cpp", "server.cpp", "axis_pass.hip", "batch.hip"]
 
 
 def _compile(src: str) -> str:

@@ -111,6 +111,7 @@ PlanOptions plan_options(const jt_plan_options *opt)
         if (opt->iterations > 0) po.iterations = opt->iterations;
         po.seed = opt->seed;
         if (opt->kind != 0) po.kind = opt->kind;
+        po.planner = opt->planner;
     }
     return po;
 }
@@ -147,7 +148,7 @@ jt_plan_s *build_plan(int d, const int *n, const double *a, const double *b, dou
 
 extern "C" {
 
-int jt_version(void) { return 123; }
+int jt_version(void) { return 124; }
 
 const char *jt_last_error(void) { return g_err.c_str(); }
 
@@ -209,6 +210,7 @@ jt_status jt_plan_info(jt_plan_t plan, int axis, jt_axis_info *info)
     info->rsvd_rounds = ax.rsvd_rounds;
     info->rel_err = ax.rel_err;
     info->fro = ax.fro;
+    info->planner = ax.planner;
     return ok();
 }
 

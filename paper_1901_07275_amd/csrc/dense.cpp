@@ -29,6 +29,20 @@ CMat matmul(const CMat &x, const CMat &y)
     return z;
 }
 
+// Column j of a column-major complex matrix as interleaved (re, im) doubles.
+static inline double *col_ptr(CMat &m, int j) { return reinterpret_cast<double *>(&m.a[(size_t)j * m.rows]); }
+
+// sum over rows [k, nr) of |c_i|^2.  The reductions in this file may be
+// reassociated (vectorized partial sums): the order is fixed by the build, so
+// results are reproducible run to run.
+static double tail_norm2(const double *c, int k, int nr)
+{
+#pragma clang fp reassociate(on)
+    double s = 0.0;
+    for (int i = 2 * k; i < 2 * nr; ++i) s += c[i] * c[i];
+    return s;
+}
+
 std::vector<int> pivoted_qr(const CMat &m_in, int steps, CMat *q_out)
 {
     CMat r = m_in;
@@ -38,25 +52,26 @@ std::vector<int> pivoted_qr(const CMat &m_in, int steps, CMat *q_out)
     std::iota(perm.begin(), perm.end(), 0);
     std::vector<std::vector<cd>> refl;  // Householder vectors (length nr, zero above k)
     std::vector<double> refl_beta;
+    // squared norms of the columns' remaining parts, downdated after every
+    // step and recomputed where the downdate has cancelled all but 1e-8 of
+    // the value last computed in full (orig)
+    std::vector<double> cn(nc), orig(nc);
+    parallel_for(nc, [&](int j) { cn[j] = orig[j] = tail_norm2(col_ptr(r, j), 0, nr); });
 
     for (int k = 0; k < steps; ++k) {
-        // pick the column of largest remaining norm (recomputed, no downdating)
+        // pick the column of largest remaining norm
         int best = k;
         double bestn = -1.0;
-        std::vector<double> cn(nc - k);
-        parallel_for(nc - k, [&](int jj) {
-            double s = 0.0;
-            for (int i = k; i < nr; ++i) s += std::norm(r(i, k + jj));
-            cn[jj] = s;
-        });
         for (int j = k; j < nc; ++j)
-            if (cn[j - k] > bestn) { bestn = cn[j - k]; best = j; }
+            if (cn[j] > bestn) { bestn = cn[j]; best = j; }
         if (best != k) {
             for (int i = 0; i < nr; ++i) std::swap(r(i, k), r(i, best));
             std::swap(perm[k], perm[best]);
+            std::swap(cn[k], cn[best]);
+            std::swap(orig[k], orig[best]);
         }
         // reflector that maps r(k:,k) to a multiple of e_k
-        double xn = std::sqrt(std::max(bestn, 0.0));
+        double xn = std::sqrt(tail_norm2(col_ptr(r, k), k, nr));
         std::vector<cd> v(nr, cd(0.0, 0.0));
         if (xn == 0.0) {
             refl.push_back(v);
@@ -70,12 +85,31 @@ std::vector<int> pivoted_qr(const CMat &m_in, int steps, CMat *q_out)
         double vv = 0.0;
         for (int i = k; i < nr; ++i) vv += std::norm(v[i]);
         double beta = (vv > 0.0) ? 2.0 / vv : 0.0;
+        const double *vd = reinterpret_cast<const double *>(v.data());
         parallel_for(nc - k, [&](int jj) {
             const int j = k + jj;
-            cd dot(0.0, 0.0);
-            for (int i = k; i < nr; ++i) dot += std::conj(v[i]) * r(i, j);
-            dot *= beta;
-            for (int i = k; i < nr; ++i) r(i, j) -= v[i] * dot;
+            double *c = col_ptr(r, j);
+            // dot = v^H c over rows [k, nr)
+            double dr0 = 0.0, di0 = 0.0;
+            {
+#pragma clang fp reassociate(on)
+                for (int i = k; i < nr; ++i) {
+                    dr0 += vd[2 * i] * c[2 * i] + vd[2 * i + 1] * c[2 * i + 1];
+                    di0 += vd[2 * i] * c[2 * i + 1] - vd[2 * i + 1] * c[2 * i];
+                }
+            }
+            const double dr = beta * dr0, di = beta * di0;
+            for (int i2 = k; i2 < nr; ++i2) {
+                const double a = vd[2 * i2], b = vd[2 * i2 + 1];
+                c[2 * i2] -= a * dr - b * di;
+                c[2 * i2 + 1] -= a * di + b * dr;
+            }
+            if (j > k) {
+                const double e = c[2 * k] * c[2 * k] + c[2 * k + 1] * c[2 * k + 1];
+                double left = cn[j] - e;
+                if (!(left > 1e-8 * orig[j])) orig[j] = left = tail_norm2(c, k + 1, nr);
+                cn[j] = left;
+            }
         });
         refl.push_back(v);
         refl_beta.push_back(beta);

@@ -7,12 +7,14 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <numeric>
 #include <stdexcept>
 #include <thread>
 
 #include "dense.h"
+#include "phase.h"
 
 namespace jt {
 
@@ -465,18 +467,31 @@ long double hilbert_weight(long double x, long double a, long double b)
 namespace {
 struct Evaluator {
     int n = 0, nu0 = 0, L = 0, Nc = 0;
+    double a = 0.0, b = 0.0;
     Rec rec;
     std::vector<ld> x, sw, invpw, q0;  // node, sqrt(omega), 1/(pi w(x)), q_0(x)
     std::vector<int> m;
     std::vector<cd> ph;  // ph[p] = exp(-2 pi i p / L)
 
+    // q_0 at node j.  Plans whose sampled columns come from the phase
+    // functions need it only for the sampled rows (lazy_q0): it is computed
+    // there from 1 - x_j and 1 + x_j instead of once for every node.
+    bool lazy_q0 = false, dbl_q = false;
+    std::vector<ld> omx, opx;
+    ld q0_at(int j) const
+    {
+        if (!lazy_q0) return q0[j];
+        return (dbl_q ? (ld)hilbert_weight_parts<double>((double)omx[j], (double)opx[j], a, b)
+                      : hilbert_weight_parts<ld>(omx[j], opx[j], a, b)) / rec.sqrt_mu0;
+    }
+
     // Walk the p and q recurrences at node j up to degree kmax, calling
-    // emit(k, p_k, q_k) for every k.
+    // emit(k, p_k, q_k) for every k (q_k = 0 without with_q).
     template <class F>
-    void walk(int j, int kmax, F emit) const
+    void walk(int j, int kmax, F emit, bool with_q = true) const
     {
         const ld xj = x[j];
-        ld pm = 0, p = 1 / rec.sqrt_mu0, qm = 0, q = q0[j];
+        ld pm = 0, p = 1 / rec.sqrt_mu0, qm = 0, q = with_q ? q0_at(j) : 0;
         for (int k = 0; k <= kmax; ++k) {
             emit(k, p, q);
             if (k == kmax) break;
@@ -539,8 +554,98 @@ struct Evaluator {
         return out;
     }
     // columns (degree offsets c = k - nu0), sorted ascending
+    // ---- phase-function columns (Section 2.2)
+    // The phase grid, each node's panel and barycentric coefficients, its
+    // offset from its DFT bin delta_j = t_j - 2 pi m_j / L, and the row scale
+    // rs_j = sqrt(omega_j / (w(x_j) sin t_j)) that turns Ptilde + i Qtilde into
+    // a row of W B; the data panel's points with their factors
+    // sqrt(w sin t), sqrt(sin t / w) / pi and q_0.
+    bool phase_cols = false;
+    std::unique_ptr<PhaseGrid> grid;
+    std::vector<BaryPoint> bp;
+    std::vector<double> delta, tn, rs;
+    ld dx[PhaseGrid::kPts], dsP[PhaseGrid::kPts], dsQ[PhaseGrid::kPts], dq0[PhaseGrid::kPts];
+
+    void set_phase_data()
+    {
+        const int D = grid->data;
+        for (int i = 0; i < PhaseGrid::kPts; ++i) {
+            const ld t = grid->point(D, i);
+            const ld sh = sinl(t / 2), ch = cosl(t / 2);
+            const ld om = 2 * sh * sh, op = 2 * ch * ch;
+            const ld wx = powl(om, (ld)a) * powl(op, (ld)b);
+            dx[i] = cosl(t);
+            dsP[i] = sqrtl(wx * sinl(t));
+            dsQ[i] = sqrtl(sinl(t) / wx) / kPi;
+            dq0[i] = hilbert_weight_parts<ld>(om, op, a, b) / rec.sqrt_mu0;
+        }
+    }
+    // Ptilde_k and Qtilde_k at the data panel's points for the ascending
+    // degrees degs (P, Q: degs.size() x kPts); with sturm, also the number of
+    // sign changes of p_0 .. p_{degs.back()} at each point (the zeros of
+    // p_{degs.back()} between that point and t = 0).
+    void data_values(const std::vector<int> &degs, std::vector<double> &P, std::vector<double> &Q,
+                     int *sturm = nullptr) const
+    {
+        constexpr int K = PhaseGrid::kPts;
+        P.assign(degs.size() * K, 0.0);
+        Q.assign(degs.size() * K, 0.0);
+        const int kmax = degs.back();
+        for (int i = 0; i < K; ++i) {
+            ld pm = 0, p = 1 / rec.sqrt_mu0, qm = 0, q = dq0[i];
+            int changes = 0;
+            ld last = p;
+            size_t ci = 0;
+            for (int k = 0; k <= kmax; ++k) {
+                if (p != 0) {
+                    if ((p < 0) != (last < 0)) ++changes;
+                    last = p;
+                }
+                while (ci < degs.size() && degs[ci] == k) {
+                    P[ci * K + i] = (double)(dsP[i] * p);
+                    Q[ci * K + i] = (double)(dsQ[i] * q);
+                    ++ci;
+                }
+                if (k == kmax) break;
+                const ld ib = rec.ibe[k + 1];
+                const ld pn = ((dx[i] - rec.al[k]) * p - rec.be[k] * pm) * ib;
+                const ld qn = ((dx[i] - rec.al[k]) * q - rec.be[k] * qm + (k == 0 ? rec.sqrt_mu0 : 0)) * ib;
+                pm = p; p = pn;
+                qm = q; q = qn;
+            }
+            if (sturm) sturm[i] = changes;
+        }
+    }
+    // Columns (degree offsets cs) from the amplitude and phase of each
+    // degree: entry = rs_j sqrt(N) exp(i (k delta_j + (a+b+1)/2 t_j + theta)),
+    // i.e. (Ptilde + i Qtilde)(t_j) exp(-2 pi i m_j k / L) with the row scale.
+    CMat cols_phase(const std::vector<int> &cs) const
+    {
+        constexpr int K = PhaseGrid::kPts;
+        const int nc = (int)cs.size();
+        std::vector<int> degs(nc);
+        for (int i = 0; i < nc; ++i) degs[i] = nu0 + cs[i];
+        std::vector<double> P, Q;
+        data_values(degs, P, Q);
+        std::vector<DegreePhase> tab(nc);
+        parallel_for(nc, [&](int i) { solve_phase(*grid, degs[i], &P[(size_t)i * K], &Q[(size_t)i * K], tab[i]); });
+        const double shift = 0.5 * (a + b + 1.0);
+        CMat out(n, nc);
+        parallel_for(n, [&](int j) {
+            for (int i = 0; i < nc; ++i) {
+                double N, th;
+                eval_phase(tab[i], bp[j], N, th);
+                const double phi = degs[i] * delta[j] + shift * tn[j] + th;
+                const double amp = rs[j] * std::sqrt(N);
+                out(j, i) = cd(amp * std::cos(phi), amp * std::sin(phi));
+            }
+        });
+        return out;
+    }
+
     CMat cols(const std::vector<int> &cs) const
     {
+        if (phase_cols && !cs.empty()) return cols_phase(cs);
         if (dbl_cols && !cs.empty()) return cols_double(cs);
         CMat out(n, (int)cs.size());
         if (cs.empty()) return out;
@@ -556,8 +661,58 @@ struct Evaluator {
         });
         return out;
     }
+    // Sampled rows in double precision (same tolerance condition as
+    // cols_double).  Blocks of up to 64 rows walk the recurrence in lock step,
+    // one degree at a time, so every degree fills a contiguous piece of its
+    // column and the per-row updates run as plain vector loops.
+    CMat rows_double(const std::vector<int> &rs) const
+    {
+        const int nr = (int)rs.size();
+        CMat out(nr, Nc);
+        constexpr int RB = 64;
+        const double p0 = (double)(1 / rec.sqrt_mu0), sm0 = (double)rec.sqrt_mu0;
+        const int nblk = (nr + RB - 1) / RB;
+        parallel_for(nblk, [&](int blk) {
+            const int i0 = blk * RB, cnt = std::min(RB, nr - i0);
+            double xx[RB], pm[RB], p[RB], qm[RB], q[RB], sp[RB], sq[RB];
+            int e[RB], mm[RB];
+            for (int i = 0; i < cnt; ++i) {
+                const int j = rs[i0 + i];
+                xx[i] = (double)x[j];
+                pm[i] = 0; p[i] = p0; qm[i] = 0; q[i] = (double)q0_at(j);
+                sp[i] = (double)sw[j];
+                sq[i] = (double)(sw[j] * invpw[j]);
+                mm[i] = m[j];
+                e[i] = (int)(((int64_t)m[j] * nu0) % L);
+            }
+            for (int k = 0; k < n; ++k) {
+                if (k >= nu0) {
+                    cd *col = &out.a[(size_t)(k - nu0) * nr + i0];
+                    for (int i = 0; i < cnt; ++i) {
+                        const cd w = ph[e[i]];
+                        const double zr = sp[i] * p[i], zi = sq[i] * q[i];
+                        col[i] = cd(zr * w.real() - zi * w.imag(), zr * w.imag() + zi * w.real());
+                        e[i] += mm[i];
+                        e[i] -= (e[i] >= L) ? L : 0;
+                    }
+                }
+                if (k == n - 1) break;
+                const double ib = rec.ibe_d[k + 1], al = rec.al_d[k], bk = rec.be_d[k];
+                const double add = (k == 0) ? sm0 : 0.0;
+                for (int i = 0; i < cnt; ++i) {
+                    const double xa = xx[i] - al;
+                    const double pn = (xa * p[i] - bk * pm[i]) * ib;
+                    const double qn = (xa * q[i] - bk * qm[i] + add) * ib;
+                    pm[i] = p[i]; p[i] = pn;
+                    qm[i] = q[i]; q[i] = qn;
+                }
+            }
+        });
+        return out;
+    }
     CMat rows(const std::vector<int> &rs) const
     {
+        if (dbl_cols && !rs.empty() && Nc > 0) return rows_double(rs);
         CMat out((int)rs.size(), Nc);
         parallel_for((int)rs.size(), [&](int i) {
             std::vector<cd> r(Nc);
@@ -575,7 +730,8 @@ static void rsvd(const Evaluator &E, double tol, const PlanOptions &opt, uint64_
     const int rmax = std::min(Nr, Nc);
     int r = std::min(rmax, std::max(4, (int)std::ceil(2.0 * std::log2((double)E.n))));
     Rng rng(seed);
-    const bool all_rows = Nr <= 2048;
+    // the a-posteriori check: every row up to 512 rows, else 512 sampled rows
+    const bool all_rows = Nr <= 512;
     std::vector<int> check_rows;
     if (all_rows) {
         check_rows.resize(Nr);
@@ -594,27 +750,45 @@ static void rsvd(const Evaluator &E, double tol, const PlanOptions &opt, uint64_
     // depend on the thread count.
     auto rel_errors = [&](const CMat &U0, const std::vector<double> &s, const CMat &Vh, int rk, int keep) {
         const int nchk = (int)check_rows.size();
-        CMat C(nchk, rk);
+        // U0 diag(s) on the check rows, real and imaginary parts apart (plain
+        // real loops below)
+        std::vector<double> Cr((size_t)nchk * rk), Ci((size_t)nchk * rk);
         for (int l = 0; l < rk; ++l)
-            for (int i = 0; i < nchk; ++i) C(i, l) = U0(check_rows[i], l) * s[l];
+            for (int i = 0; i < nchk; ++i) {
+                const cd z = U0(check_rows[i], l) * s[l];
+                Cr[(size_t)l * nchk + i] = z.real();
+                Ci[(size_t)l * nchk + i] = z.imag();
+            }
+        auto norm2 = [&](const double *xr, const double *xi) {
+            double e0 = 0.0, e1 = 0.0;
+            for (int i = 0; i < nchk; ++i) {
+                e0 += xr[i] * xr[i];
+                e1 += xi[i] * xi[i];
+            }
+            return e0 + e1;
+        };
         constexpr int kChunk = 64;
         const int nchunk = (Nc + kChunk - 1) / kChunk;
         std::vector<double> pk(nchunk, 0.0), pf(nchunk, 0.0);
         parallel_for(nchunk, [&](int ch) {
-            std::vector<cd> res(nchk);
+            std::vector<double> rr(nchk), ri(nchk);
             double ek = 0.0, ef = 0.0;
             const int c1 = std::min(Nc, (ch + 1) * kChunk);
             for (int c = ch * kChunk; c < c1; ++c) {
-                for (int i = 0; i < nchk; ++i) res[i] = Zc(i, c);
-                for (int l = 0; l < rk; ++l) {
-                    if (l == keep)
-                        for (int i = 0; i < nchk; ++i) ek += std::norm(res[i]);
-                    const cd vl = Vh(l, c);
-                    const cd *cl = &C.a[(size_t)l * nchk];
-                    for (int i = 0; i < nchk; ++i) res[i] -= cl[i] * vl;
+                for (int i = 0; i < nchk; ++i) {
+                    rr[i] = Zc(i, c).real();
+                    ri[i] = Zc(i, c).imag();
                 }
-                double e = 0.0;
-                for (int i = 0; i < nchk; ++i) e += std::norm(res[i]);
+                for (int l = 0; l < rk; ++l) {
+                    if (l == keep) ek += norm2(rr.data(), ri.data());
+                    const double vr = Vh(l, c).real(), vi = Vh(l, c).imag();
+                    const double *cr = &Cr[(size_t)l * nchk], *ci = &Ci[(size_t)l * nchk];
+                    for (int i = 0; i < nchk; ++i) {
+                        rr[i] -= cr[i] * vr - ci[i] * vi;
+                        ri[i] -= cr[i] * vi + ci[i] * vr;
+                    }
+                }
+                const double e = norm2(rr.data(), ri.data());
                 ef += e;
                 if (keep >= rk) ek += e;
             }
@@ -732,6 +906,7 @@ static void check_axis_args(int n, double a, double b, double tol, const PlanOpt
     if (!(tol >= 1e-14) || !(tol <= 1e-2)) throw std::invalid_argument("tol must lie in [1e-14, 1e-2]");
     if (opt.nu0 < 1 || opt.nu0 > kMaxNu0) throw std::invalid_argument("nu0 must lie in [1, 64]");
     if (opt.kind != 1 && opt.kind != 2) throw std::invalid_argument("kind must be 1 (first) or 2 (second)");
+    if (opt.planner < 0 || opt.planner > 2) throw std::invalid_argument("planner must be 0, 1 or 2");
 }
 
 // Sizes, direct-block width and seed of an axis; the evaluator's shape.
@@ -748,10 +923,117 @@ static void start_axis(AxisPlan &ax, Evaluator &E, int n, double a, double b, do
     ax.seed = opt.seed ? opt.seed : mix_key(n, a, b, tol);
     ax.kind = opt.kind;
     E.n = n; E.nu0 = ax.nu0; E.L = L; E.Nc = n - ax.nu0;
+    E.a = a; E.b = b;
     E.dbl_cols = tol >= 1e-10;
+    // double quadrature only where the weight's exponents are mild: near -1
+    // the tanh-sinh tail of the far-end singularity overflows double range
+    E.dbl_q = E.dbl_cols && a > -0.5 && b > -0.5;
     E.rec = recurrence(n + 1, a, b);
     E.x.resize(n); E.sw.resize(n); E.invpw.resize(n); E.q0.resize(n); E.m.resize(n);
     ax.t.resize(n); ax.x.resize(n); ax.omega.resize(n); ax.bins.resize(n);
+}
+
+// Phase functions (Section 2.2) give the nodes, the weights and the sampled
+// columns of uniform plans for |a|, |b| < 1/2 (the range Section 2.2 treats)
+// at tolerances of 1e-8 and looser: the tables carry the phase to about
+// 1e-14 lam absolute, so the nodes to about 1e-13 and the entries to about
+// 1e-9 at n = 16384, an order below such a tolerance (the recurrence stays for
+// the sampled rows and the direct block).  Planner 1 never uses them,
+// planner 2 wherever allowed, planner 0 (automatic) from kPhaseAuto points
+// on, where they are the faster way (measured crossover near 1024).
+constexpr int kPhaseAuto = 1024;
+constexpr int kPhaseMin = 64;
+static bool phase_allowed(int n, double a, double b, double tol, const PlanOptions &opt)
+{
+    if (opt.planner == 1 || n < kPhaseMin || !(tol >= 1e-8)) return false;
+    if (!(std::fabs(a) < 0.5) || !(std::fabs(b) < 0.5)) return false;
+    if (n - std::min(opt.nu0, n) > 0 && opt.nu0 < 27) return false;  // the tables start at degree 27
+    return opt.planner == 2 || n >= kPhaseAuto;
+}
+
+// Nodes and weights from the phase of degree n: P~_n = M cos psi vanishes
+// where psi = pi/2 (mod pi), psi increases, so the j-th node solves
+//   psi(t) = psi(t_s) + g + (j - K) pi,   g = (pi/2 - psi(t_s)) mod pi,
+// with K the number of nodes below a data point t_s (the sign changes of
+// p_0 .. p_n there, by the Sturm property of orthogonal polynomials).
+// Newton on the interpolated phase; the Gauss-Jacobi weight in t is
+// pi / psi'(t_j) = pi N(t_j) / W (so omega_j = that times w(x_j) sin t_j).
+// Returns false (and the caller uses the recurrence) if any node fails to
+// converge inside the grid, the nodes do not increase, or P~_n computed by the
+// recurrence at three of them is not small.
+static bool phase_nodes(const Evaluator &E, int n, std::vector<ld> &tl, std::vector<ld> &wl)
+{
+    constexpr int K = PhaseGrid::kPts;
+    const PhaseGrid &g = *E.grid;
+    std::vector<double> P, Q;
+    int sturm[K];
+    E.data_values(std::vector<int>{n}, P, Q, sturm);
+    DegreePhase ph;
+    solve_phase(g, n, P.data(), Q.data(), ph);
+    // a data point where P~_n is well away from zero (its zero count is then sure)
+    int is = -1;
+    for (int i = K / 2; i < K - 1 && is < 0; ++i)
+        if (std::fabs(P[i]) > 0.25 * std::sqrt(P[i] * P[i] + Q[i] * Q[i])) is = i;
+    if (is < 0) return false;
+    const double lam = ph.lam, W = 2.0 * lam / (double)kPi;
+    const double ts = g.point(g.data, is);
+    const BaryPoint bs = bary_point(g, ts);
+    double Ns, ths;
+    eval_phase(ph, bs, Ns, ths);
+    // psi(t_s) mod pi in long double (lam t_s reaches lam pi / 2)
+    const ld psis = (ld)lam * (ld)ts + (ld)ths;
+    const ld g0 = fmodl(fmodl(kPi / 2 - psis, kPi) + kPi, kPi);
+    const int Kz = sturm[is];
+    tl.assign(n, 0);
+    wl.assign(n, 0);
+    std::atomic<int> bad(0);
+    const double lo = g.ends.front(), hi = g.ends.back();
+    parallel_for(n, [&](int j) {
+        // lam (t - t_s) + theta(t) = R_j
+        const double R = (double)((ld)ths + g0 + (ld)(j - Kz) * kPi);
+        double t = ts + (R - ths) / lam;
+        bool conv = false;
+        for (int it = 0; it < 40; ++it) {
+            t = std::min(hi, std::max(lo, t));
+            const BaryPoint bpt = bary_point(g, t);
+            double N, th;
+            eval_phase(ph, bpt, N, th);
+            const double f = lam * (t - ts) + th - R;
+            const double dt = f / (W / N);
+            t -= dt;
+            if (std::fabs(dt) <= 1e-15 * std::max(1.0, t)) {
+                conv = t > lo && t < hi;
+                break;
+            }
+        }
+        if (!conv) {
+            bad.fetch_add(1);
+            return;
+        }
+        const BaryPoint bpt = bary_point(g, t);
+        double N, th;
+        eval_phase(ph, bpt, N, th);
+        const ld tj = t;
+        const ld sh = sinl(tj / 2), ch = cosl(tj / 2);
+        const ld wsin = powl(2 * sh * sh, (ld)E.a) * powl(2 * ch * ch, (ld)E.b) * sinl(tj);
+        tl[j] = tj;
+        wl[j] = (ld)kPi * (ld)N / (ld)W * wsin;
+    });
+    if (bad.load()) return false;
+    for (int j = 1; j < n; ++j)
+        if (!(tl[j] > tl[j - 1])) return false;
+    // spot checks with the recurrence: P~_n(t_j) ~ 0 relative to the amplitude
+    for (int j : {0, n / 2, n - 1}) {
+        ld pn, pn1, dpn;
+        eval_top(E.rec, n, cosl(tl[j]), pn, pn1, dpn);
+        const ld sh = sinl(tl[j] / 2), ch = cosl(tl[j] / 2);
+        const ld amp = sqrtl(powl(2 * sh * sh, (ld)E.a) * powl(2 * ch * ch, (ld)E.b) * sinl(tl[j]));
+        const BaryPoint bpt = bary_point(g, (double)tl[j]);
+        double N, th;
+        eval_phase(ph, bpt, N, th);
+        if (!(fabsl(amp * pn) <= 1e-8L * sqrtl((ld)N))) return false;
+    }
+    return true;
 }
 
 // Per-point values at angle t with row scale sw: the point, its bin
@@ -770,12 +1052,19 @@ static void set_point(AxisPlan &ax, Evaluator &E, int j, ld t, ld sw, ld om)
     ax.x[j] = (double)xj;
     ax.omega[j] = (double)om;
     ax.bins[j] = E.m[j];
-    // double quadrature only where the weight's exponents are mild: near -1
-    // the tanh-sinh tail of the far-end singularity overflows double range
-    const bool dbl_q = E.dbl_cols && ax.a > -0.5 && ax.b > -0.5;
-    if (E.Nc > 0 || ax.kind == 2)
-        E.q0[j] = (dbl_q ? (ld)hilbert_weight_parts<double>((double)omx, (double)opx, ax.a, ax.b)
-                         : hilbert_weight_parts<ld>(omx, opx, ax.a, ax.b)) / E.rec.sqrt_mu0;
+    if (E.phase_cols) {
+        E.bp[j] = bary_point(*E.grid, (double)t);
+        E.delta[j] = (double)(t - 2 * kPi * E.m[j] / ax.L);
+        E.tn[j] = (double)t;
+        E.rs[j] = (double)(sw / sqrtl(wx * sinl(t)));
+    }
+    if (E.lazy_q0) {
+        E.omx[j] = omx;
+        E.opx[j] = opx;
+    } else if (E.Nc > 0 || ax.kind == 2) {
+        E.q0[j] = (E.dbl_q ? (ld)hilbert_weight_parts<double>((double)omx, (double)opx, ax.a, ax.b)
+                           : hilbert_weight_parts<ld>(omx, opx, ax.a, ax.b)) / E.rec.sqrt_mu0;
+    }
 }
 
 // Everything after the points: bin table, direct block, DFT phases and the
@@ -803,7 +1092,7 @@ static void finish_axis(AxisPlan &ax, Evaluator &E, const PlanOptions &opt)
     parallel_for(n, [&](int j) {
         E.walk(j, ax.nu0 - 1, [&](int k, ld p, ld q) {
             ax.WV[(size_t)k * n + j] = (double)(second ? E.sw[j] * q * E.invpw[j] : E.sw[j] * p);
-        });
+        }, second);
     });
     // DFT phase table of eq. (45): exp(-2 pi i p / L), exact integer phase
     E.ph.resize(L);
@@ -825,10 +1114,28 @@ void build_axis(AxisPlan &ax, int n, double a, double b, double tol, const PlanO
     Evaluator E;
     start_axis(ax, E, n, a, b, tol, opt);
     std::vector<ld> tl, wl;
+    bool phase = phase_allowed(n, a, b, tol, opt);
+    if (phase) {
+        E.grid.reset(new PhaseGrid(n, a, b));
+        E.set_phase_data();
+        phase = phase_nodes(E, n, tl, wl);
+    }
     // double-precision nodes and weights are kept at tolerances of 1e-7 and
     // looser: their error (weights to about 3e-17 n^2 relative, from the
     // double x next to +-1) stays two orders below such a tolerance
-    nodes_ld(E.rec, n, a, b, tl, wl, tol < 1e-7);
+    if (!phase) nodes_ld(E.rec, n, a, b, tl, wl, tol < 1e-7);
+    // sampled columns from the phase tables when every node lies on the grid
+    if (phase && E.Nc > 0) {
+        bool inside = true;
+        for (int j = 0; j < n; ++j) inside = inside && E.grid->panel_of((double)tl[j]) >= 0;
+        if (inside) {
+            E.phase_cols = true;
+            E.lazy_q0 = ax.kind == 1;
+            E.bp.resize(n); E.delta.resize(n); E.tn.resize(n); E.rs.resize(n);
+            if (E.lazy_q0) { E.omx.resize(n); E.opx.resize(n); }
+        }
+    }
+    ax.planner = phase ? 2 : 1;
     // uniform transform: rows weighted by sqrt(omega_j) (Section 3.1, eq. (37))
     parallel_for(n, [&](int j) { set_point(ax, E, j, tl[j], sqrtl(wl[j]), wl[j]); });
     finish_axis(ax, E, opt);

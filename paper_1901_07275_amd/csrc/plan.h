@@ -29,6 +29,7 @@ struct AxisPlan {
     int max_per_bin = 0;
     bool points = false;  // nonuniform: given points, no quadrature weights (forward only)
     int kind = 1;         // 1: Ptilde (first kind), 2: Qtilde (second kind, forward only)
+    int planner = 1;      // 1: recurrence throughout; 2: phase functions for nodes, weights, sampled columns
     double a = 0.0, b = 0.0, tol = 0.0;
     uint64_t seed = 0;
     std::vector<double> t, x, omega;  // nodes ascending in t, Gauss-Jacobi weights (0 for given points)
@@ -57,6 +58,7 @@ struct PlanOptions {
     int iterations = 2;     // repetitions of steps 2-3 (Section 2.1 uses two)
     uint64_t seed = 0;      // 0: derive from (n, a, b, tol)
     int kind = 1;           // 1: first kind, 2: second kind
+    int planner = 0;        // 0: automatic, 1: recurrence only, 2: phase functions wherever allowed
 };
 
 // Build one axis.  Throws std::runtime_error on bad input or non-convergence.

@@ -28,7 +28,7 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_version():
-    assert jt.version() == 123
+    assert jt.version() == 124
 
 
 @pytest.mark.parametrize("n,ab,tol", [

@@ -29,12 +29,19 @@ def test_nodes_and_weights_match_oracle(orc, n, a, b):
     # Tolerances of 1e-7 and looser keep the double Newton roots and double
     # Christoffel weights: x to rounding, weights to about 3e-17 n^2 relative
     # (double x next to +-1), two orders below such a tolerance.
+    # From 1024 points at tolerances of 1e-8 and looser (|a|, |b| < 1/2) the
+    # automatic planner takes the nodes from the phase function (Section 2.2):
+    # x to a few units of rounding, weights to 3e-12 relative.
     for tol, wtol in ((1e-8, 1e-12), (1e-7, max(1e-12, 3e-17 * n * n))):
-        t, x, w = plan1(n, a, b, tol).nodes(0)
-        assert np.all(np.diff(t) > 0)
-        np.testing.assert_allclose(x, xo, rtol=0, atol=4e-16)
-        np.testing.assert_allclose(w, wo, rtol=wtol, atol=0)
-        np.testing.assert_allclose(np.cos(t), x, rtol=0, atol=4e-16)
+        for planner in (0, 1):
+            P = plan1(n, a, b, tol, planner=planner)
+            t, x, w = P.nodes(0)
+            phase = P.info(0)["planner"] == 2
+            assert phase == (planner == 0 and n >= 1024 and abs(a) < 0.5 and abs(b) < 0.5)
+            assert np.all(np.diff(t) > 0)
+            np.testing.assert_allclose(x, xo, rtol=0, atol=1e-15 if phase else 4e-16)
+            np.testing.assert_allclose(w, wo, rtol=3e-12 if phase else wtol, atol=0)
+            np.testing.assert_allclose(np.cos(t), x, rtol=0, atol=4e-16)
 
 
 @pytest.mark.parametrize("n,a,b", [(1024, 0.25, -0.35), (1000, 0.0, 0.0), (256, 0.3, 0.3)])
