@@ -306,13 +306,20 @@ struct Geo {
 #ifndef JT_TW_MODE_F64_SHORT_INV
 #define JT_TW_MODE_F64_SHORT_INV 3
 #endif
+// fp32 inverse passes over lines of up to 256 points: computed twiddles
+// (mode 3) keep the kernel at 162 registers, three waves per SIMD (on
+// 1024-point lines the same change, for three waves there too, was measured
+// slower: 59/64 -> 85/99 us per inverse pass)
+#ifndef JT_TW_MODE_F32_SHORT_INV
+#define JT_TW_MODE_F32_SHORT_INV 3
+#endif
 template <class T, int LOG2L, int FWD>
 constexpr int tw_mode()
 {
     if constexpr (sizeof(T) == 8)
         return LOG2L <= 8 ? (FWD ? JT_TW_MODE_F64_SHORT_FWD : JT_TW_MODE_F64_SHORT_INV) : JT_TW_MODE_F64;
     else if constexpr (Geo<LOG2L>::BLOCK > 256) return 3;  // big lines: too few registers per lane
-    else if constexpr (!FWD) return 0;
+    else if constexpr (!FWD) return LOG2L <= 8 ? JT_TW_MODE_F32_SHORT_INV : 0;
     else return LOG2L <= 8 ? 1 : JT_TW_MODE_F32_FWD;
 }
 
@@ -827,9 +834,20 @@ __device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, 
         // the nodes of each owned bin m (at most two in almost every plan), as
         // padded LDS slots packed j_a | j_b << 16 (0xffff: none); the same for
         // every term, so they are read once
-        // (fp64 only up to 256 points: measured faster there, much slower
-        // on 1024-point lines, where the registers are short)
-        constexpr bool kBP = Geo<LOG2L>::BLOCK <= 256 && (sizeof(T) == 4 || LOG2L <= 8);
+        // (fp64 only below 256 points: much slower on 1024-point lines, where
+        // the registers are short; at 256 points the 16 extra registers take
+        // the fp64 inverse over 256 (one wave per SIMD instead of two) and the
+        // fp32 inverse over 170 (two instead of three): measured on 256^3,
+        // 1100 -> 910 us (fp64) and 640 -> 495 us (fp32, with computed
+        // twiddles) per inverse pass without them)
+#ifndef JT_BP_L256_F64
+#define JT_BP_L256_F64 0
+#endif
+#ifndef JT_BP_L256_F32
+#define JT_BP_L256_F32 0
+#endif
+        constexpr bool kBP = Geo<LOG2L>::BLOCK <= 256 && (sizeof(T) == 4 || LOG2L <= 8) &&
+                             (LOG2L != 8 || (sizeof(T) == 4 ? JT_BP_L256_F32 : JT_BP_L256_F64));
         const bool two = kBP && a.max_per_bin <= 2;
         unsigned bpair[VL][kBP ? 16 : 1];
 #pragma unroll
