@@ -69,16 +69,18 @@ def batch_source_hash() -> str:
                         "launch.h", "./tuning.json"))
 
 
-def measured_batch_traffic(workload: str, items: int):
+def measured_batch_traffic(workload: str, items: int, dense_items: int):
     """HBM bytes per launch of the batch kernel on this batched workload from
-    the committed rocprofv3 summary, or None (other workload, or sources
-    changed since the counters were taken)."""
+    the committed rocprofv3 summary, or None (other workload, another
+    FFT-versus-dense split of the items, or sources changed since the
+    counters were taken)."""
     prof = os.path.join(ROOT, "profiles", "batch_kernel_%s_traffic.json" % workload.replace("batched-", ""))
     try:
         rec = json.load(open(prof))
     except (OSError, ValueError):
         return None
-    if rec.get("source_sha256_16") != batch_source_hash() or rec.get("items") != items:
+    if (rec.get("source_sha256_16") != batch_source_hash() or rec.get("items") != items
+            or rec.get("dense_items") != dense_items):
         return None
     return float(rec["hbm_bytes"])
 
@@ -436,6 +438,7 @@ def batched(args) -> int:
     t64 = e0.elapsed_time(e1) if sel else float("nan")
     coeffs_sel = int(sum(sizes[i] for i in sel))
     info = B.info()
+    dense_items = int(sum(1 for p in plans if p.info(0)["nu0"] == p.info(0)["n"]))
     line = {
         "metric": "coeffs/s, ragged batch of %d independent %s transforms in one persistent launch"
                   % (len(items), "1D" if args.workload == "batched-1d" else "2D"),
@@ -445,8 +448,8 @@ def batched(args) -> int:
         "config": {"workload": args.workload, "items": len(items), "coeffs": coeffs, "tol": 1e-7,
                    "units": info["units"], "grid": info["grid"], "threads": info["threads"],
                    "plan_seconds": t_plan, "graph": True, "tuning": tuning.get("source"),
-                   "dense_items": int(sum(1 for p in plans if p.info(0)["nu0"] == p.info(0)["n"]))},
-        "roofline": dict(roof, traffic=measured_batch_traffic(args.workload, len(items)),
+                   "dense_items": dense_items},
+        "roofline": dict(roof, traffic=measured_batch_traffic(args.workload, len(items), dense_items),
                          kernel="batch_kernel<float>", bytes_per_launch=nbytes, fft_flops_per_launch=fft_flops,
                          mfma_flops_per_launch=mfma_flops, fracs=fracs,
                          peak_times_ms={k: v * 1e3 for k, v in times.items()}),

@@ -158,9 +158,10 @@ struct Flight {
     size_t table_off = 0;
     hipEvent_t done = nullptr;         // outputs copied back
     // the launch's error word (bit 0: a wait for a previous pass timed out,
-    // bit 1: unsupported length), copied back with the outputs; on the heap
-    // so that its address survives moving the flight into the queue
-    std::unique_ptr<uint32_t> err_word{new uint32_t(0)};
+    // bit 1: unsupported length), copied back with the outputs into a slot of
+    // the server's pinned ring (a copy into pageable memory would block the
+    // scheduler until the flight's outputs are back)
+    uint32_t *err_word = nullptr;
     double coeffs = 0;
 };
 
@@ -174,6 +175,12 @@ struct jt_server_s {
     jt_dtype tin = JT_F32, tout = JT_F32;
     int device = 0, cus = 1;
     hipStream_t s_in = nullptr, s_out = nullptr, s_comp[2] = {nullptr, nullptr};
+    // pinned host words for the flights' error words, used round robin: more
+    // slots than flights in flight, and flights retire in launch order, so a
+    // slot is free again when its turn comes
+    uint32_t *err_ring = nullptr;
+    int err_slots = 0;
+    uint64_t launches_made = 0;
     int next_comp = 0;
 
     std::mutex mu;
@@ -512,6 +519,8 @@ struct jt_server_s {
         if (take.empty()) return false;
         Flight f;
         f.reqs = take;
+        f.err_word = &err_ring[launches_made++ % (uint64_t)err_slots];
+        *f.err_word = 0;
         std::vector<jt::QueueItem> items;
         for (Request *r : take) {
             jt::QueueItem it;
@@ -566,7 +575,7 @@ struct jt_server_s {
             if (e == hipSuccess)
                 e = hipMemcpyAsync(r->hout, arena_ptr + r->out_off, r->out_bytes, hipMemcpyDeviceToHost, s_out);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(f.err_word.get(), b.counters + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s_out);
+            e = hipMemcpyAsync(f.err_word, b.counters + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s_out);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&f.done, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventRecord(f.done, s_out);
         // the events above only order the streams; the flight's own event marks completion
@@ -675,9 +684,12 @@ jt_status jt_server_create(void *dev_arena, size_t bytes, const jt_server_option
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->s_out, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->s_comp[0], hipStreamNonBlocking);
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->s_comp[1], hipStreamNonBlocking);
+        S->err_slots = o.max_inflight + 2;
+        if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&S->err_ring), sizeof(uint32_t) * S->err_slots);
         if (e != hipSuccess) {
             for (hipStream_t s : {S->s_in, S->s_out, S->s_comp[0], S->s_comp[1]})
                 if (s) (void)hipStreamDestroy(s);
+            if (S->err_ring) (void)hipHostFree(S->err_ring);
             return fail(JT_EDEVICE, std::string("server streams: ") + hipGetErrorString(e));
         }
         jt_server_s *raw = S.get();
@@ -796,6 +808,7 @@ jt_status jt_server_destroy(jt_server_t S)
         if (kv.second->uploaded) (void)hipEventDestroy(kv.second->uploaded);
     for (hipStream_t s : {S->s_in, S->s_out, S->s_comp[0], S->s_comp[1]})
         if (s) (void)hipStreamDestroy(s);
+    if (S->err_ring) (void)hipHostFree(S->err_ring);
     delete S;
     return ok();
 }
