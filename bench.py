@@ -667,7 +667,7 @@ def main() -> int:
                          "rocprofv3 FETCH_SIZE/WRITE_SIZE against known bytes")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(one GPU's share of the work is the whole workload); run with --gpus 1", file=sys.stderr)
         return 2
 
