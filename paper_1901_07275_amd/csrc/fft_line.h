@@ -966,10 +966,12 @@ __device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, 
 #pragma unroll
             for (int q = 0; q < 16; ++q) part[pv[h] + G::P * q] = acc[h][q];
         __syncthreads();
+        // each group adds up (and below stores) only the slots q = sgrp mod S
 #pragma unroll
         for (int h = 0; h < VL; ++h)
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
+                if ((q % S) != sgrp) continue;  // uniform
                 double t = 0.0;
                 for (int s2 = 0; s2 < S; ++s2)
                     t += reinterpret_cast<const double *>(smem + (s2 * G::LPB + slot) * G::BUF)[pv[h] + G::P * q];
