@@ -113,3 +113,35 @@ def test_phase_plan_is_deterministic():
     p2 = plan1(3000, 0.2, 0.1, 1e-7, planner=2)
     for x, y in zip(p1.factors(0), p2.factors(0)):
         assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("a,b", [(0.2, -0.1), (0.45, -0.45), (-0.3, 0.3)])
+@pytest.mark.parametrize("k", [27, 100, 1000])
+def test_wronskian_of_the_normalized_pair(orc, a, b, k):
+    """The tables take psi' = W / N with W = 2 lam / pi, lam = k + (a+b+1)/2,
+    for the pair (Ptilde_k, Qtilde_k) as the oracle defines it: checked here on
+    the oracle alone, W = P Q' - P' Q from central differences at several t."""
+    lam = k + (a + b + 1) / 2
+    t = np.array([0.4, 1.1, np.pi / 2, 2.3, 2.9])
+    h = 1e-5
+    tt = np.concatenate([t - h, t, t + h])
+    P = orc.ptilde(k + 1, a, b, tt)[:, k].reshape(3, -1)
+    Q = orc.qtilde(k + 1, a, b, tt)[:, k].reshape(3, -1)
+    dP = (P[2] - P[0]) / (2 * h)
+    dQ = (Q[2] - Q[0]) / (2 * h)
+    W = P[1] * dQ - dP * Q[1]
+    # central differences: error ~ h^2 lam^3 relative to lam
+    np.testing.assert_allclose(W, 2 * lam / np.pi, rtol=max(1e-6, 2 * h * h * lam ** 2))
+
+
+def test_phase_nodes_follow_the_amplitude(orc):
+    """At a zero of Ptilde_n the weight pi / psi' equals pi N / W; with W = 2 lam / pi
+    and N = Ptilde^2 + Qtilde^2 = Qtilde^2 there, the Gauss weights in t are
+    pi^2 Qtilde_n(t_j)^2 / (2 lam): checked on the oracle's own rule."""
+    n, a, b = 300, 0.3, -0.2
+    _, x, w = orc.matrix(n, a, b)
+    t = np.arccos(x)
+    Q = orc.qtilde(n + 1, a, b, t)[:, n]
+    lam = n + (a + b + 1) / 2
+    wt = w / ((1 - x) ** a * (1 + x) ** b * np.sin(t))
+    np.testing.assert_allclose(wt, np.pi ** 2 * Q ** 2 / (2 * lam), rtol=1e-9)
