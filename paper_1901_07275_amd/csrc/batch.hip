@@ -117,9 +117,9 @@ __device__ __attribute__((noinline)) void run_unit(const PassDesc &d, const Work
         cpx<T> *vs = smem + vb * S * G::LPB * G::BUF;
         const cpx<T> *tw = reinterpret_cast<const cpx<T> *>(a.tw);
         if (a.forward)
-            pass_lines<T, LOG2L, 1, VL>(a, line0, line_end, S, sgrp, (int)threadIdx.x % G::BLOCK, vs, tw);
+            pass_lines<T, LOG2L, 1, VL, false>(a, line0, line_end, S, sgrp, (int)threadIdx.x % G::BLOCK, vs, tw);
         else
-            pass_lines<T, LOG2L, 0, VL>(a, line0, line_end, S, sgrp, (int)threadIdx.x % G::BLOCK, vs, tw);
+            pass_lines<T, LOG2L, 0, VL, false>(a, line0, line_end, S, sgrp, (int)threadIdx.x % G::BLOCK, vs, tw);
     }
 }
 

@@ -508,7 +508,10 @@ __device__ __forceinline__ void fft_line(cpx<T> (*v)[16], cpx<T> *buf, const int
 // these groups; tw is the L-entry twiddle table (global or LDS).  Every
 // thread of the block must call this with the same S and the same rank.
 // A thread carries VL lanes of its line (VL > 1 only when S == 1).
-template <class T, int LOG2L, int FWD, int VL = 1>
+// OWN_SUM: each group adds up only the partial sums of the slots it stores
+// (the one-pass kernel; measured slower inside the persistent batch kernel,
+// whose register allocation it changes, so that one sums every slot).
+template <class T, int LOG2L, int FWD, int VL = 1, bool OWN_SUM = true>
 __device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, unsigned line_end, int S, int sgrp,
                                            int tid, cpx<T> *smem, const cpx<T> *tw)
 {
@@ -966,12 +969,13 @@ __device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, 
 #pragma unroll
             for (int q = 0; q < 16; ++q) part[pv[h] + G::P * q] = acc[h][q];
         __syncthreads();
-        // each group adds up (and below stores) only the slots q = sgrp mod S
+        // with OWN_SUM, each group adds up (and below stores) only the slots
+        // q = sgrp mod S
 #pragma unroll
         for (int h = 0; h < VL; ++h)
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
-                if ((q % S) != sgrp) continue;  // uniform
+                if (OWN_SUM && (q % S) != sgrp) continue;  // uniform
                 double t = 0.0;
                 for (int s2 = 0; s2 < S; ++s2)
                     t += reinterpret_cast<const double *>(smem + (s2 * G::LPB + slot) * G::BUF)[pv[h] + G::P * q];
