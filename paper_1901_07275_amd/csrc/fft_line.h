@@ -511,7 +511,10 @@ __device__ __forceinline__ void fft_line(cpx<T> (*v)[16], cpx<T> *buf, const int
 // OWN_SUM: each group adds up only the partial sums of the slots it stores
 // (the one-pass kernel; measured slower inside the persistent batch kernel,
 // whose register allocation it changes, so that one sums every slot).
-template <class T, int LOG2L, int FWD, int VL = 1, bool OWN_SUM = true>
+// PF (forward, single-lane threads): bit 0 loads the next term's v_l while
+// the current term gathers, bit 1 requests the term's u_l before its FFT.
+// Both hold 16 more complex values per thread across the FFT.
+template <class T, int LOG2L, int FWD, int VL = 1, bool OWN_SUM = true, int PF = 0>
 __device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, unsigned line_end, int S, int sgrp,
                                            int tid, cpx<T> *smem, const cpx<T> *tw)
 {
@@ -636,12 +639,7 @@ __device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, 
 #ifndef JT_HOIST_BINS
 #define JT_HOIST_BINS 1
 #endif
-#ifndef JT_PF_V
-#define JT_PF_V 0
-#endif
-#ifndef JT_PF_U
-#define JT_PF_U 0
-#endif
+        constexpr bool kPFV = (PF & 1) && VL == 1, kPFU = (PF & 2) && VL == 1;
         // LDS slots of y[m_j] for the owned nodes (the same for every term);
         // kept in registers except on the longest lines, which have none to spare
 #ifndef JT_HOIST_F64
@@ -664,7 +662,7 @@ __device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, 
         }
         // factors v_l of the next term, loaded while the current term gathers
         cpx<T> fv[VL][16];
-        if constexpr (JT_PF_V) {
+        if constexpr (kPFV) {
             const int l = (sgrp < rank) ? sgrp : rank - 1;
 #pragma unroll
             for (int h = 0; h < VL; ++h)
@@ -680,12 +678,12 @@ __device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, 
             for (int h = 0; h < VL; ++h)
 #pragma unroll
                 for (int q = 0; q < 16; ++q) {
-                    const cpx<T> f = JT_PF_V ? fv[h][q] : vf[l * G::L + pv[h] + G::P * q];
+                    const cpx<T> f = kPFV ? fv[h][q] : vf[l * G::L + pv[h] + G::P * q];
                     v[h][q] = {f.x * x[h][q], f.y * x[h][q]};
                 }
             // u_l for the gather, requested before the FFT so that it arrives meanwhile
-            cpx<T> uu[VL][JT_PF_U ? 16 : 1];
-            if constexpr (JT_PF_U) {
+            cpx<T> uu[VL][kPFU ? 16 : 1];
+            if constexpr (kPFU) {
                 const cpx<T> *ul = uf + l * n;
 #pragma unroll
                 for (int h = 0; h < VL; ++h)
@@ -705,7 +703,7 @@ __device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, 
                     const int m = pv[h] + G::P * q;
                     if (m <= G::L / 2) buf[pad(m)] = v[h][q];
                 }
-            if constexpr (JT_PF_V) {
+            if constexpr (kPFV) {
                 const int ln0 = (it + 1) * S + sgrp;
                 const int ln = ln0 < rank ? ln0 : rank - 1;
 #pragma unroll
@@ -724,7 +722,7 @@ __device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, 
                         for (int q = 0; q < 16; ++q) {
                             const int j = pv[h] + G::P * q;
                             const cpx<T> y = buf[kHB ? bix[h][q % (kHB ? 16 : 1)] : pad(a.bins[j])];
-                            const cpx<T> u = JT_PF_U ? uu[h][q % (JT_PF_U ? 16 : 1)] : ul[j];
+                            const cpx<T> u = kPFU ? uu[h][q % (kPFU ? 16 : 1)] : ul[j];
                             acc[h][q] += (double)(u.x * y.x - u.y * y.y);
                         }
                 } else {
@@ -735,7 +733,7 @@ __device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, 
                             const int j = pv[h] + G::P * q;
                             if (j < n) {
                                 const cpx<T> y = buf[kHB ? bix[h][q % (kHB ? 16 : 1)] : pad(a.bins[j])];
-                                const cpx<T> u = JT_PF_U ? uu[h][q % (JT_PF_U ? 16 : 1)] : ul[j];
+                                const cpx<T> u = kPFU ? uu[h][q % (kPFU ? 16 : 1)] : ul[j];
                                 acc[h][q] += (double)(u.x * y.x - u.y * y.y);
                             }
                         }

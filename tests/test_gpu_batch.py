@@ -210,3 +210,56 @@ def test_batch_round_trip_property(jt):
     b = back.cpu().numpy()
     for i, x in enumerate(xs):
         assert relerr(F.item(b, i), x) <= 4e-5
+
+
+LONG_SHAPES = [(16000,), (300,), (9000,), (16384,), (64, 80), (12000,)]
+LONG_AB = [((0.2, -0.1),), ((0.1, 0.2),), ((-0.4, 0.3),), ((0.45, -0.45),), ((0.0, 0.1), (0.2, -0.2)), ((0.3, 0.3),)]
+
+
+def _check_long(jt, orc, P, out_np):
+    for i, (s, ab, d) in enumerate(zip(P.shapes, P.abs_, P.dirs)):
+        x = P.xs_cast[i]
+        if len(s) == 1 and s[0] > 4096:
+            ref = orc.apply1d_fp64(x, ab[0], transpose=(d == jt.INVERSE))
+        else:
+            ref = orc.forward(x, ab) if d == jt.FORWARD else orc.inverse(x, ab)
+        e = relerr(P.item(out_np, i), ref)
+        assert e <= 2e-5, (i, s, d, e)
+
+
+@pytest.mark.parametrize("tin_name,tout_name", [("F64", "F64"), ("F32", "F32")])
+def test_batch_long_lines(jt, orc, tin_name, tout_name):
+    """1D items of 8193 to 16384 points (one 16384-point line per block, two
+    lanes per thread) beside short and multi-axis items: parity with the
+    oracle in both directions and both dtypes, the same bits on every run, in
+    place and on graph replays."""
+    tin, tout = getattr(jt, tin_name), getattr(jt, tout_name)
+    dirs = [jt.FORWARD if i % 2 else jt.INVERSE for i in range(len(LONG_SHAPES))]
+    print("long lines %s -> %s" % (tin_name, tout_name), flush=True)
+    P = Prepared(jt, LONG_SHAPES, LONG_AB, dirs, 1e-7, 1, tin, tout, seed=11)
+    P.batch.run(P.inp, P.out)
+    torch.cuda.synchronize()
+    assert P.batch.errors() == 0
+    first = P.out.cpu().numpy().copy()
+    _check_long(jt, orc, P, first)
+    for rep in range(3):
+        P.out.fill_(float("nan"))
+        P.batch.run(P.inp, P.out)
+        torch.cuda.synchronize()
+        assert np.array_equal(P.out.cpu().numpy(), first), "run %d differs" % rep
+    if tin == tout:
+        buf = P.inp.clone()
+        P.batch.run(buf, buf)
+        torch.cuda.synchronize()
+        assert np.array_equal(buf.cpu().numpy(), first), "in place differs"
+    P.batch.capture(P.inp, P.out)
+    for rep in range(3):
+        P.out.fill_(float("nan"))
+        junk = torch.randn(1 << 20, device=P.out.device).sum()
+        torch.cuda.synchronize()
+        P.batch.replay()
+        torch.cuda.synchronize()
+        assert P.batch.errors() == 0
+        assert np.array_equal(P.out.cpu().numpy(), first), "replay %d differs" % rep
+        del junk
+    orc.clear_cache()
