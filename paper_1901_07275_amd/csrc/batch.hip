@@ -118,6 +118,19 @@ constexpr int batch_prefetch()
     else return (LOG2L <= JT_BATCH_PF_V_MAX ? 1 : 0) | (JT_BATCH_PF_U ? 2 : 0);
 }
 
+// Inverse FFT units: fp32 single-lane lines up to JT_BATCH_PF_INV_MAX =
+// log2 L request the term's v_l before the FFT (the 4096-item ragged
+// batches run inverse: 1D 3.59 -> 3.51 ms, 2D on the FFT path 24.9 -> 21.5
+// ms).
+#ifndef JT_BATCH_PF_INV_MAX
+#define JT_BATCH_PF_INV_MAX 13
+#endif
+template <class T, int LOG2L>
+constexpr int batch_prefetch_inv()
+{
+    return (sizeof(T) == 4 && LOG2L <= JT_BATCH_PF_INV_MAX) ? 4 : 0;
+}
+
 template <class T, int LOG2L>
 __device__ __attribute__((noinline)) void run_unit(const PassDesc &d, const WorkUnit &w, const BatchLaunch &b, cpx<T> *smem)
 {
@@ -140,7 +153,8 @@ __device__ __attribute__((noinline)) void run_unit(const PassDesc &d, const Work
             pass_lines<T, LOG2L, 1, VL, false, batch_prefetch<T, LOG2L>()>(a, line0, line_end, S, sgrp,
                                                                            (int)threadIdx.x % G::BLOCK, vs, tw);
         else
-            pass_lines<T, LOG2L, 0, VL, false>(a, line0, line_end, S, sgrp, (int)threadIdx.x % G::BLOCK, vs, tw);
+            pass_lines<T, LOG2L, 0, VL, false, batch_prefetch_inv<T, LOG2L>()>(a, line0, line_end, S, sgrp,
+                                                                               (int)threadIdx.x % G::BLOCK, vs, tw);
     }
 }
 

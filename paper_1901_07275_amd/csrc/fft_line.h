@@ -511,9 +511,10 @@ __device__ __forceinline__ void fft_line(cpx<T> (*v)[16], cpx<T> *buf, const int
 // OWN_SUM: each group adds up only the partial sums of the slots it stores
 // (the one-pass kernel; measured slower inside the persistent batch kernel,
 // whose register allocation it changes, so that one sums every slot).
-// PF (forward, single-lane threads): bit 0 loads the next term's v_l while
-// the current term gathers, bit 1 requests the term's u_l before its FFT.
-// Both hold 16 more complex values per thread across the FFT.
+// PF (single-lane threads): forward, bit 0 loads the next term's v_l while
+// the current term gathers and bit 1 requests the term's u_l before its FFT;
+// inverse, bit 2 requests the term's v_l before its FFT.  Each holds 16 more
+// complex values per thread across the FFT.
 template <class T, int LOG2L, int FWD, int VL = 1, bool OWN_SUM = true, int PF = 0>
 __device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, unsigned line_end, int S, int sgrp,
                                            int tid, cpx<T> *smem, const cpx<T> *tw)
@@ -865,6 +866,7 @@ __device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, 
                 }
                 bpair[h][q % (kBP ? 16 : 1)] = w;
             }
+        constexpr bool kPFI = (PF & 4) && VL == 1;
         for (int it = 0; it < iters; ++it) {
             const int l0 = it * S + sgrp;
             const bool keep = l0 < rank;
@@ -942,6 +944,14 @@ __device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, 
                         v[h][q] = z;
                     }
             }
+            // v_l of this term, requested before the FFT (PF bit 2)
+            cpx<T> fi[VL][kPFI ? 16 : 1];
+            if constexpr (kPFI) {
+#pragma unroll
+                for (int h = 0; h < VL; ++h)
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) fi[h][q] = vf[l * G::L + pv[h] + G::P * q];
+            }
             sync_line<G::TPL>();
             fft_line<T, LOG2L, VL>(v, buf, pv, twd);
             if (keep) {
@@ -950,7 +960,7 @@ __device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, 
 #pragma unroll
                     for (int q = 0; q < 16; ++q) {
                         const int k = pv[h] + G::P * q;
-                        const cpx<T> f = vf[l * G::L + k];
+                        const cpx<T> f = kPFI ? fi[h][q % (kPFI ? 16 : 1)] : vf[l * G::L + k];
                         acc[h][q] += (double)(f.x * v[h][q].x - f.y * v[h][q].y);
                     }
             }
