@@ -835,20 +835,21 @@ __device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, 
             }
         // the nodes of each owned bin m (at most two in almost every plan), as
         // padded LDS slots packed j_a | j_b << 16 (0xffff: none); the same for
-        // every term, so they are read once
-        // (fp64 only below 256 points: much slower on 1024-point lines, where
-        // the registers are short; at 256 points the 16 extra registers take
-        // the fp64 inverse over 256 (one wave per SIMD instead of two) and the
-        // fp32 inverse over 170 (two instead of three): measured on 256^3,
-        // 1100 -> 910 us (fp64) and 640 -> 495 us (fp32, with computed
-        // twiddles) per inverse pass without them)
+        // every term, so they are read once.  Only where 16 more registers
+        // keep the kernel's occupancy: fp32, and fp64 below 256 points and at
+        // 1024 (2D 1024^2 fp64 inverse passes 81.0/99.2 -> 80.5/98.1 us).  At
+        // 256 points they would take the fp64 inverse over 256 registers (one
+        // wave per SIMD instead of two) and the fp32 inverse over 170 (two
+        // instead of three): measured on 256^3, 1100 -> 910 us (fp64) and
+        // 640 -> 495 us (fp32, with computed twiddles) per inverse pass
+        // without them.
 #ifndef JT_BP_L256_F64
 #define JT_BP_L256_F64 0
 #endif
 #ifndef JT_BP_L256_F32
 #define JT_BP_L256_F32 0
 #endif
-        constexpr bool kBP = Geo<LOG2L>::BLOCK <= 256 && (sizeof(T) == 4 || LOG2L <= 8) &&
+        constexpr bool kBP = Geo<LOG2L>::BLOCK <= 256 && (sizeof(T) == 4 || LOG2L <= 8 || LOG2L == 10) &&
                              (LOG2L != 8 || (sizeof(T) == 4 ? JT_BP_L256_F32 : JT_BP_L256_F64));
         const bool two = kBP && a.max_per_bin <= 2;
         unsigned bpair[VL][kBP ? 16 : 1];
