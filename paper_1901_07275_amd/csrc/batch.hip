@@ -98,13 +98,15 @@ __device__ __attribute__((noinline)) void run_dense(const PassDesc &d, const Wor
         dense_lines<T, 0>(a, (unsigned)uni(w.line0), end, rows, reinterpret_cast<T *>(smem));
 }
 
-// Factor prefetch in the forward FFT units (pass_lines' PF bits).  The
-// kernel's occupancy is fixed at two waves per SIMD by its block size and
-// LDS, so registers up to 256 per thread cost nothing here, unlike in the
-// one-pass kernel.  fp32 single-lane lines request u_l before the FFT
-// (4096-item ragged 1D batch: 3.16 -> 2.99 ms) and, up to JT_BATCH_PF_V_MAX
-// = log2 L, also load the next v_l during the gather (the same batch's 2D
-// items on the FFT path: 21.0 -> 17.0 ms); fp64 has no registers to spare.
+// Options of the forward FFT units (pass_lines' OPT bits).  The kernel's
+// occupancy is fixed at two waves per SIMD by its block size and LDS, so
+// registers up to 256 per thread cost nothing here, unlike in the one-pass
+// kernel.  fp32 single-lane lines request u_l before the FFT (4096-item
+// ragged 1D batch: 3.16 -> 2.99 ms) and, up to JT_BATCH_PF_V_MAX = log2 L,
+// also load the next v_l during the gather (the same batch's 2D items on the
+// FFT path: 21.0 -> 17.0 ms); fp64 has no registers to spare.  fp32 units
+// also take the direct block in its node-contiguous form (the ragged 1D
+// batch: 2.99 -> 2.80 ms; fp64 always does).
 #ifndef JT_BATCH_PF_V_MAX
 #define JT_BATCH_PF_V_MAX 12
 #endif
@@ -112,10 +114,10 @@ __device__ __attribute__((noinline)) void run_dense(const PassDesc &d, const Wor
 #define JT_BATCH_PF_U 1
 #endif
 template <class T, int LOG2L>
-constexpr int batch_prefetch()
+constexpr int batch_fwd_opts()
 {
     if constexpr (sizeof(T) != 4) return 0;
-    else return (LOG2L <= JT_BATCH_PF_V_MAX ? 1 : 0) | (JT_BATCH_PF_U ? 2 : 0);
+    else return (LOG2L <= JT_BATCH_PF_V_MAX ? 1 : 0) | (JT_BATCH_PF_U ? 2 : 0) | 8;
 }
 
 // Inverse FFT units: fp32 single-lane lines up to JT_BATCH_PF_INV_MAX =
@@ -126,7 +128,7 @@ constexpr int batch_prefetch()
 #define JT_BATCH_PF_INV_MAX 13
 #endif
 template <class T, int LOG2L>
-constexpr int batch_prefetch_inv()
+constexpr int batch_inv_opts()
 {
     return (sizeof(T) == 4 && LOG2L <= JT_BATCH_PF_INV_MAX) ? 4 : 0;
 }
@@ -150,10 +152,10 @@ __device__ __attribute__((noinline)) void run_unit(const PassDesc &d, const Work
         cpx<T> *vs = smem + vb * S * G::LPB * G::BUF;
         const cpx<T> *tw = reinterpret_cast<const cpx<T> *>(a.tw);
         if (a.forward)
-            pass_lines<T, LOG2L, 1, VL, false, batch_prefetch<T, LOG2L>()>(a, line0, line_end, S, sgrp,
+            pass_lines<T, LOG2L, 1, VL, false, batch_fwd_opts<T, LOG2L>()>(a, line0, line_end, S, sgrp,
                                                                            (int)threadIdx.x % G::BLOCK, vs, tw);
         else
-            pass_lines<T, LOG2L, 0, VL, false, batch_prefetch_inv<T, LOG2L>()>(a, line0, line_end, S, sgrp,
+            pass_lines<T, LOG2L, 0, VL, false, batch_inv_opts<T, LOG2L>()>(a, line0, line_end, S, sgrp,
                                                                                (int)threadIdx.x % G::BLOCK, vs, tw);
     }
 }
