@@ -297,11 +297,13 @@ struct Geo {
 #define JT_TW_MODE_F32_FWD 3
 #endif
 // fp64 lines of up to 256 points (one radix-16 pass after the first, many
-// lines per pass): measured on 256^3, forward passes are fastest with the
-// twiddles from global memory (532 against 980 us per pass), inverse passes
-// with computed ones (1081 against 1130 us).
+// lines per pass): computed twiddles in both directions, measured on 256^3.
+// Forward passes took 532 us with the twiddles from global memory against
+// 980 us computed when first measured; with the node-contiguous direct
+// block they take 500-520 us from global memory and 465-478 us computed.
+// Inverse passes: 1081 against 1130 us, computed ones faster.
 #ifndef JT_TW_MODE_F64_SHORT_FWD
-#define JT_TW_MODE_F64_SHORT_FWD 2
+#define JT_TW_MODE_F64_SHORT_FWD 3
 #endif
 #ifndef JT_TW_MODE_F64_SHORT_INV
 #define JT_TW_MODE_F64_SHORT_INV 3
