@@ -807,7 +807,13 @@ __device__ __forceinline__ void pass_lines(const AxisLaunch &a, unsigned line0, 
         for (int h = 0; h < VL; ++h)
 #pragma unroll
             for (int q = 0; q < 16; ++q) acc[h][q] = 0.0;
-        constexpr int KC = Geo<LOG2L>::BLOCK <= 256 ? 8 : 2;  // fewer live sums on register-poor long lines
+        // degrees per chunk: 4 in the one-pass kernel (against 8: 2D 1024^2
+        // fp64 inverse passes 80.9/97.7 -> 79.2/96.3 us, 3D 256^3 fp64 about
+        // 12 us faster per pass; 16 took the fp32 256-point inverse over 170
+        // registers), 8 in the persistent kernel (OWN_SUM false), whose
+        // 2048- and 4096-point units spill more with 4, and 2 on the
+        // register-poor long lines
+        constexpr int KC = Geo<LOG2L>::BLOCK <= 256 ? (OWN_SUM ? 4 : 8) : 2;
         const int nchunks = (nu0 + KC - 1) / KC;
         const int rounds = (nchunks + S - 1) / S;
         // The line buffer is free until the first term.  It holds, in order:
